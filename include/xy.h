@@ -1,0 +1,166 @@
+/*
+ * xy.h -- C ABI of the MI355X Swendsen-Wang / PCC engine for the 2D classical
+ * XY model (Komura & Okabe, "Large-scale Monte Carlo simulation of
+ * two-dimensional classical XY model using multiple GPUs", arXiv:1210.6116).
+ *
+ * The model is Eq. (Hc): H = -J sum_<ij> cos(theta_i - theta_j) on an L x L
+ * square lattice with periodic boundary conditions, J = 1.  One sweep is the
+ * Swendsen-Wang multi-cluster update with Wolff's embedded-cluster formalism
+ * (introduction: the SW and PCC paragraphs): draw a mirror direction r, activate
+ * every link (i, j) with probability p = 1 - exp(min(0, -2 beta (s_i.r)(s_j.r))),
+ * label the connected components of the active links, and reflect every spin of
+ * each component, s -> s - 2 (s.r) r, with probability 1/2.  After every sweep
+ * the energy, the magnetisation and the helicity-modulus sums are reduced
+ * (the e / s definitions of the helicity-modulus paragraph); the generalized
+ * probability-changing-cluster controller (the PCC paragraph) moves beta by
+ * +-dbeta after each window according to whether beta*Upsilon is below or
+ * above 0.636508.
+ *
+ * Conventions for every call:
+ *   - The return value is XY_OK (0) or a negative XY_E* code; nothing throws
+ *     or aborts across the ABI.  xy_last_error() gives a message for the last
+ *     failing call on the calling thread.
+ *   - Invalid arguments return XY_EINVAL and change nothing.  A HIP error
+ *     returns XY_EDEVICE and poisons the handle: every later call on it except
+ *     xy_free returns XY_ESTATE.
+ *   - Work is enqueued on the handle's HIP stream.  Calls that return data to
+ *     host memory synchronize that stream before returning; the others are
+ *     asynchronous.
+ *   - A handle must not be driven from two threads at once.
+ *   - Site index i = y*L + x (x fastest).  Host arrays are plain C arrays of
+ *     the stated length, owned by the caller.
+ */
+#ifndef XY_H
+#define XY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    XY_OK = 0,
+    XY_EINVAL = -1,  /* bad argument */
+    XY_ENOMEM = -2,  /* device or host allocation failed, or the arena is too small */
+    XY_EDEVICE = -3, /* a HIP call failed; the handle is poisoned */
+    XY_ESTATE = -4,  /* the handle is poisoned or in the wrong state for the call */
+    XY_EBUDGET = -5  /* reserved for admission by memory budget (serving) */
+};
+
+enum { XY_START_HOT = 0 /* independent uniform angles */, XY_START_COLD = 1 /* theta = 0 */ };
+
+typedef struct xy_handle xy_handle;
+
+/* One lattice (replica).  A handle holds n of them, each with its own size,
+ * temperature and random stream; they are updated together. */
+typedef struct {
+    int64_t L;          /* side; a power of two, 2 <= L <= 65536 */
+    double beta;        /* inverse temperature (J = 1), 0 <= beta <= 1e4 */
+    uint64_t seed;      /* 64-bit Philox4x32-10 key */
+    uint32_t replica;   /* stream id (Philox counter word 1) */
+    int32_t label_bits; /* 32, 64, or 0 = automatic (64 iff L*L >= 2^32) */
+    int32_t start;      /* XY_START_HOT or XY_START_COLD */
+    int32_t tile_rows;  /* rows of a labelling tile: 16, 32, 64, or 0 = automatic */
+} xy_params;
+
+/* Observables of one configuration, or means over a PCC window (all per site;
+ * paper: Eq. (Hc), the helicity-modulus e and s over x-links, <m^2> = chi/L^2). */
+typedef struct {
+    uint64_t sweep;     /* sweeps completed by the replica when the sample was taken */
+    double beta;        /* beta the sweep ran at (window means: beta after the step) */
+    double E;           /* H / N, both link directions */
+    double m2;          /* |sum_i s_i / N|^2 */
+    double ex, sx;      /* sum over x-links of cos / sin(theta_i - theta_j), over N */
+    double ey, sy;      /* the same over y-links */
+    double ups_x;       /* ex - beta N sx^2 (sample of the helicity modulus) */
+    uint64_t near_ties; /* bond decisions of the sweep with |u - p| < 1e-9 */
+} xy_obs;
+
+/* Generalized PCC controller (paper: the PCC paragraph and the simulation
+ * paragraph: windows of 1000 MCS, dbeta = 0.0005, target 0.636508). */
+typedef struct {
+    int64_t window;      /* sweeps per PCC step, >= 1 */
+    double dbeta0;       /* step of the first PCC step, > 0 */
+    double dbeta_min;    /* floor of the halving schedule, >= 0 */
+    int64_t halve_every; /* PCC steps between halvings of dbeta; 0 = never */
+    double target;       /* critical beta*Upsilon, e.g. 0.636508 */
+} xy_pcc;
+
+/* Device bytes that xy_alloc needs for these n replicas (arena size). */
+int xy_bytes_required(const xy_params *p, int32_t n, size_t *bytes);
+
+/* Creates a handle for n >= 1 replicas p[0..n-1] and initialises their spins
+ * (hot or cold start) at sweep 0.  hip_stream: the hipStream_t to enqueue on,
+ * or NULL for a stream the library creates.  arena: device memory of at least
+ * xy_bytes_required() bytes that the caller owns and keeps alive until
+ * xy_free (e.g. a torch tensor), or NULL to let the library allocate.
+ * On success *out receives the handle. */
+int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_t arena_bytes,
+             xy_handle **out);
+
+/* Runs nsweeps >= 0 sweeps of every replica at its current beta.
+ * trace: NULL, or host memory for nsweeps * n xy_obs, filled as
+ * trace[k * n + rep] with the observables after sweep k (synchronizes). */
+int xy_sweep(xy_handle *h, int64_t nsweeps, xy_obs *trace);
+
+/* Observables of every replica's current configuration (n xy_obs, host;
+ * synchronizes).  near_ties is 0; sweep is the replica's sweep count. */
+int xy_measure(xy_handle *h, xy_obs *out);
+
+/* Runs nsteps >= 1 PCC steps of c->window sweeps each, updating every
+ * replica's beta on the device after each window.  window_mean: NULL, or host
+ * memory for nsteps * n xy_obs receiving the window means (beta = the new
+ * beta) as window_mean[k * n + rep] (synchronizes). */
+int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_mean);
+
+/* Releases the handle and whatever the library allocated.  xy_free(NULL) is OK. */
+int xy_free(xy_handle *h);
+
+/* ---- inspection and control (tests, tooling) ---------------------------- */
+
+/* Copies replica rep's spins to / from host arrays of N = L*L floats.  Spins
+ * set must be unit vectors within 1e-3 (the bond test's error bound assumes
+ * it); XY_EINVAL otherwise. */
+int xy_get_state(xy_handle *h, int32_t rep, float *cos_out, float *sin_out);
+int xy_set_state(xy_handle *h, int32_t rep, const float *cos_in, const float *sin_in);
+
+/* Canonical cluster labels (minimum site index of each cluster) of the most
+ * recent sweep of replica rep, as N int64 values (host; synchronizes). */
+int xy_get_labels(xy_handle *h, int32_t rep, int64_t *out);
+
+/* Active-link bit planes of the most recent sweep of replica rep: bit i of
+ * word i/32 of bx (by) is the link (i, right(i)) ((i, down(i))).  Host arrays
+ * of ceil(N/32) uint32 each (synchronizes). */
+int xy_get_bonds(xy_handle *h, int32_t rep, uint32_t *bx, uint32_t *by);
+
+/* beta of replica rep: set (takes effect from the next sweep) / read. */
+int xy_set_beta(xy_handle *h, int32_t rep, double beta);
+int xy_get_beta(xy_handle *h, int32_t rep, double *beta);
+
+/* Sweep counter of replica rep and its mirror direction r for the next sweep. */
+int xy_get_sweep(xy_handle *h, int32_t rep, uint64_t *sweep, double r[2]);
+
+/* Standalone labelling of a given link set (the same kernels as the sweep):
+ * d_bx, d_by are device bit planes as in xy_get_bonds; d_labels receives N
+ * canonical labels (uint32 if label_bits == 32, uint64 if 64) in device memory.
+ * Enqueued on hip_stream (NULL = the default stream); asynchronous. */
+int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint32_t *d_bx,
+                   const uint32_t *d_by, void *d_labels, void *hip_stream);
+
+/* Per-kernel timing with HIP events on the handle's stream: enable (1) or
+ * disable (0) recording; read the accumulated milliseconds and launch counts
+ * of each kernel class (XY_K_* below) and reset them (synchronizes). */
+enum { XY_K_BONDS = 0, XY_K_MERGE = 1, XY_K_FLIP = 2, XY_K_FUSED = 3, XY_K_COUNT = 4 };
+int xy_timing(xy_handle *h, int32_t enable);
+int xy_timing_read(xy_handle *h, double *ms, int64_t *launches);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *xy_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XY_H */

@@ -1,0 +1,185 @@
+"""ctypes binding of libxy.so (include/xy.h): argument marshalling only.
+
+Every step of the sweep runs in the library's HIP kernels.  torch is imported
+first so that the process holds a single HIP runtime (libxy.so and torch then
+share it), and it supplies device memory (the arena tensor) and streams.
+There is no fallback: if libxy.so is missing or fails to load, this raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime that libxy.so binds to)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxy.so")
+
+XY_OK, XY_EINVAL, XY_ENOMEM, XY_EDEVICE, XY_ESTATE, XY_EBUDGET = 0, -1, -2, -3, -4, -5
+XY_START_HOT, XY_START_COLD = 0, 1
+XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_COUNT = 0, 1, 2, 3, 4
+KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused")
+
+
+class XYError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("xy error %d: %s" % (code, msg))
+        self.code = code
+
+
+class xy_params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int64), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32), ("label_bits", ctypes.c_int32), ("start", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32)]
+
+
+class xy_obs(ctypes.Structure):
+    _fields_ = [("sweep", ctypes.c_uint64), ("beta", ctypes.c_double), ("E", ctypes.c_double),
+                ("m2", ctypes.c_double), ("ex", ctypes.c_double), ("sx", ctypes.c_double),
+                ("ey", ctypes.c_double), ("sy", ctypes.c_double), ("ups_x", ctypes.c_double),
+                ("near_ties", ctypes.c_uint64)]
+
+
+class xy_pcc(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int64), ("dbeta0", ctypes.c_double), ("dbeta_min", ctypes.c_double),
+                ("halve_every", ctypes.c_int64), ("target", ctypes.c_double)]
+
+
+OBS_DTYPE = np.dtype([("sweep", np.uint64), ("beta", np.float64), ("E", np.float64), ("m2", np.float64),
+                      ("ex", np.float64), ("sx", np.float64), ("ey", np.float64), ("sy", np.float64),
+                      ("ups_x", np.float64), ("near_ties", np.uint64)])
+assert OBS_DTYPE.itemsize == ctypes.sizeof(xy_obs)
+
+_lib = None
+
+# name -> (restype, argtypes); the C signatures of include/xy.h
+_P = ctypes.POINTER
+_SIGS = {
+    "xy_bytes_required": (ctypes.c_int, [_P(xy_params), ctypes.c_int32, _P(ctypes.c_size_t)]),
+    "xy_alloc": (ctypes.c_int, [_P(xy_params), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_size_t, _P(ctypes.c_void_p)]),
+    "xy_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "xy_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_pcc_step": (ctypes.c_int, [ctypes.c_void_p, _P(xy_pcc), ctypes.c_int64, ctypes.c_void_p]),
+    "xy_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "xy_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_get_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "xy_get_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_set_beta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double]),
+    "xy_get_beta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double)]),
+    "xy_get_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_uint64), ctypes.c_void_p]),
+    "xy_label_links": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "xy_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_last_error": (ctypes.c_char_p, []),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def load():
+    """Loads libxy.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libxy.so is not built (%s); run paper_1210_6116_amd/build.py" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != XY_OK:
+        raise XYError(rc, load().xy_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ------------------------------------------------- the C calls, same names
+def xy_bytes_required(params) -> int:
+    arr = (xy_params * len(params))(*params)
+    out = ctypes.c_size_t(0)
+    _check(load().xy_bytes_required(arr, len(params), ctypes.byref(out)))
+    return out.value
+
+
+def xy_alloc(params, stream=None, arena=None, arena_bytes=0):
+    arr = (xy_params * len(params))(*params)
+    h = ctypes.c_void_p()
+    _check(load().xy_alloc(arr, len(params), stream, arena, arena_bytes, ctypes.byref(h)))
+    return h
+
+
+def xy_sweep(h, nsweeps: int, trace: np.ndarray | None = None):
+    _check(load().xy_sweep(h, nsweeps, None if trace is None else _ptr(trace)))
+
+
+def xy_measure(h, out: np.ndarray):
+    _check(load().xy_measure(h, _ptr(out)))
+
+
+def xy_pcc_step(h, pcc: xy_pcc, nsteps: int, window_mean: np.ndarray | None = None):
+    _check(load().xy_pcc_step(h, ctypes.byref(pcc), nsteps, None if window_mean is None else _ptr(window_mean)))
+
+
+def xy_free(h):
+    _check(load().xy_free(h))
+
+
+def xy_get_state(h, rep: int, c: np.ndarray, s: np.ndarray):
+    _check(load().xy_get_state(h, rep, _ptr(c), _ptr(s)))
+
+
+def xy_set_state(h, rep: int, c: np.ndarray, s: np.ndarray):
+    _check(load().xy_set_state(h, rep, _ptr(c), _ptr(s)))
+
+
+def xy_get_labels(h, rep: int, out: np.ndarray):
+    _check(load().xy_get_labels(h, rep, _ptr(out)))
+
+
+def xy_get_bonds(h, rep: int, bx: np.ndarray, by: np.ndarray):
+    _check(load().xy_get_bonds(h, rep, _ptr(bx), _ptr(by)))
+
+
+def xy_set_beta(h, rep: int, beta: float):
+    _check(load().xy_set_beta(h, rep, beta))
+
+
+def xy_get_beta(h, rep: int) -> float:
+    b = ctypes.c_double(0.0)
+    _check(load().xy_get_beta(h, rep, ctypes.byref(b)))
+    return b.value
+
+
+def xy_get_sweep(h, rep: int):
+    t = ctypes.c_uint64(0)
+    r = np.zeros(2)
+    _check(load().xy_get_sweep(h, rep, ctypes.byref(t), _ptr(r)))
+    return t.value, r
+
+
+def xy_label_links(L: int, label_bits: int, tile_rows: int, d_bx: int, d_by: int, d_labels: int, stream=None):
+    _check(load().xy_label_links(L, label_bits, tile_rows, d_bx, d_by, d_labels, stream))
+
+
+def xy_timing(h, enable: bool):
+    _check(load().xy_timing(h, int(enable)))
+
+
+def xy_timing_read(h):
+    ms = np.zeros(XY_K_COUNT)
+    n = np.zeros(XY_K_COUNT, dtype=np.int64)
+    _check(load().xy_timing_read(h, _ptr(ms), _ptr(n)))
+    return ms, n
+
+
+def xy_last_error() -> str:
+    return load().xy_last_error().decode()

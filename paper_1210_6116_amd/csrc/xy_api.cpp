@@ -1,0 +1,679 @@
+// xy_api.cpp -- host side of the C ABI declared in include/xy.h: parameter
+// checks, the device memory layout of a handle, and the per-sweep launch
+// sequence (bonds + tile labelling, merge across tiles, flip + reductions).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/xy.h"
+#include "xy_device.hpp"
+#include "xy_launch.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kTraceChunk = 256;  // sweeps (or PCC steps) per trace copy-back
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int ilog2(int64_t v)
+{
+    int k = 0;
+    while ((int64_t(1) << k) < v) ++k;
+    return k;
+}
+
+struct Resolved {
+    int64_t L, N;
+    int32_t TW, TH, ntx, nty;
+    int64_t ntiles;
+};
+
+// Per-replica byte layout inside the arena.
+struct RepLayout {
+    size_t c, s, lab[2], bx[2], by[2], coins, edge[2], partials, end;
+};
+
+struct Plan {
+    int32_t n = 0, label_bits = 32, max_th = 1;
+    bool pingpong = true;
+    std::vector<Resolved> res;
+    std::vector<RepLayout> lay;
+    size_t off_reps = 0, off_state = 0, off_tile_rep = 0, off_obs = 0, total = 0;
+    int64_t total_tiles = 0;
+};
+
+int check_params(const xy_params *p, int32_t n)
+{
+    if (!p) return fail(XY_EINVAL, "params pointer is NULL");
+    if (n < 1 || n > (1 << 20)) return fail(XY_EINVAL, "n_replicas=%d outside [1, 2^20]", n);
+    for (int32_t k = 0; k < n; ++k) {
+        const xy_params &q = p[k];
+        if (q.L < 2 || q.L > 65536 || (q.L & (q.L - 1)) != 0)
+            return fail(XY_EINVAL, "replica %d: L=%lld is not a power of two in [2, 65536]", k, (long long)q.L);
+        if (!(q.beta >= 0.0 && q.beta <= 1e4))
+            return fail(XY_EINVAL, "replica %d: beta=%g outside [0, 1e4]", k, q.beta);
+        if (q.label_bits != 0 && q.label_bits != 32 && q.label_bits != 64)
+            return fail(XY_EINVAL, "replica %d: label_bits=%d is not 0, 32 or 64", k, q.label_bits);
+        if (q.label_bits == 32 && q.L * q.L >= (int64_t(1) << 32))
+            return fail(XY_EINVAL, "replica %d: L=%lld needs 64-bit labels", k, (long long)q.L);
+        if (q.start != XY_START_HOT && q.start != XY_START_COLD)
+            return fail(XY_EINVAL, "replica %d: start=%d unknown", k, q.start);
+        if (q.tile_rows != 0 && q.tile_rows != 16 && q.tile_rows != 32 && q.tile_rows != 64)
+            return fail(XY_EINVAL, "replica %d: tile_rows=%d is not 0, 16, 32 or 64", k, q.tile_rows);
+    }
+    return XY_OK;
+}
+
+int make_plan(const xy_params *p, int32_t n, Plan &P)
+{
+    int rc = check_params(p, n);
+    if (rc) return rc;
+    P.n = n;
+    bool need64 = false, want32 = false, want64 = false;
+    int64_t maxN = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const int64_t N = p[k].L * p[k].L;
+        maxN = std::max(maxN, N);
+        if (N >= (int64_t(1) << 32)) need64 = true;
+        if (p[k].label_bits == 32) want32 = true;
+        if (p[k].label_bits == 64) want64 = true;
+    }
+    if (want32 && (need64 || want64)) return fail(XY_EINVAL, "replicas disagree on the label width");
+    P.label_bits = (need64 || want64) ? 64 : 32;
+    P.pingpong = maxN < (int64_t(1) << 30);
+    const int lb = P.label_bits / 8;
+    size_t off = 0;
+    P.res.resize(n);
+    P.lay.resize(n);
+    P.total_tiles = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        Resolved &r = P.res[k];
+        r.L = p[k].L;
+        r.N = r.L * r.L;
+        int rows = p[k].tile_rows ? p[k].tile_rows : 32;
+        if (P.label_bits == 64) rows = std::min(rows, 32);
+        r.TW = (int32_t)std::min<int64_t>(r.L, 64);
+        r.TH = (int32_t)std::min<int64_t>(r.L, rows);
+        r.ntx = (int32_t)(r.L / r.TW);
+        r.nty = (int32_t)(r.L / r.TH);
+        r.ntiles = (int64_t)r.ntx * r.nty;
+        P.max_th = std::max(P.max_th, r.TH);
+        P.total_tiles += r.ntiles;
+        RepLayout &l = P.lay[k];
+        const size_t words = (size_t)std::max<int64_t>(1, (r.N + 31) / 32);
+        l.c = off;
+        off = align_up(off + (size_t)r.N * 4);
+        l.s = off;
+        off = align_up(off + (size_t)r.N * 4);
+        for (int q = 0; q < 2; ++q) {
+            if (q == 1 && !P.pingpong) {
+                l.lab[1] = l.lab[0];
+                l.bx[1] = l.bx[0];
+                l.by[1] = l.by[0];
+                l.edge[1] = l.edge[0];
+                continue;
+            }
+            l.lab[q] = off;
+            off = align_up(off + (size_t)r.N * lb);
+            l.bx[q] = off;
+            off = align_up(off + words * 4);
+            l.by[q] = off;
+            off = align_up(off + words * 4);
+            l.edge[q] = off;
+            off = align_up(off + (size_t)r.ntiles * (r.TH + r.TW) * sizeof(float2));
+        }
+        l.coins = off;
+        off = align_up(off + std::max<size_t>(words, 4) * 4);
+        l.partials = off;
+        off = align_up(off + (size_t)r.ntiles * xy::kNumSums * sizeof(double));
+        l.end = off;
+    }
+    P.off_reps = off;
+    off = align_up(off + n * sizeof(xy::RepDesc));
+    P.off_state = off;
+    off = align_up(off + n * sizeof(xy::RepState));
+    P.off_tile_rep = off;
+    if (n > 1) off = align_up(off + (size_t)P.total_tiles * sizeof(uint32_t));
+    P.off_obs = off;
+    off = align_up(off + (size_t)(2 * kTraceChunk + 1) * n * sizeof(xy_obs));
+    P.total = off;
+    return XY_OK;
+}
+
+}  // namespace
+
+struct xy_handle {
+    Plan plan;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *arena = nullptr;
+    bool own_arena = false;
+    std::vector<xy::RepDesc> reps;
+    xy::RepDesc *d_reps = nullptr;
+    xy::RepState *d_state = nullptr;
+    uint32_t *d_tile_rep = nullptr;
+    xy_obs *d_trace = nullptr, *d_wmean = nullptr, *d_meas = nullptr;
+    bool poisoned = false;
+    // timing
+    bool timing = false;
+    struct Ev {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> ev_used, ev_free;
+    double ms[XY_K_COUNT] = {0, 0, 0, 0};
+    int64_t launches[XY_K_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int hip_fail(xy_handle *h, hipError_t e, const char *what)
+{
+    if (h) h->poisoned = true;
+    return fail(XY_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHECK(h, expr)                                    \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #expr); \
+    } while (0)
+
+int check_handle(xy_handle *h)
+{
+    if (!h) return fail(XY_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(XY_ESTATE, "handle was poisoned by an earlier device error");
+    return XY_OK;
+}
+
+xy::Launch launch_all(xy_handle *h)
+{
+    xy::Launch lc;
+    lc.reps = h->d_reps;
+    lc.tile_rep = h->d_tile_rep;
+    lc.nrep = h->plan.n;
+    lc.label_bits = h->plan.label_bits;
+    lc.max_th = h->plan.max_th;
+    lc.gtile0 = 0;
+    lc.gtile_end = h->plan.total_tiles;
+    return lc;
+}
+
+// Runs `launch` bracketed by timing events when timing is on.
+template <typename F>
+hipError_t timed(xy_handle *h, int kind, F launch)
+{
+    if (!h->timing) return launch();
+    xy_handle::Ev ev;
+    if (!h->ev_free.empty()) {
+        ev = h->ev_free.back();
+        h->ev_free.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev.a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&ev.b);
+        if (e != hipSuccess) return e;
+    }
+    ev.kind = kind;
+    hipError_t e = hipEventRecord(ev.a, h->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev.b, h->stream);
+    h->ev_used.push_back(ev);
+    return e;
+}
+
+// Enqueues one sweep of every replica.
+int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa)
+{
+    const xy::Launch lc = launch_all(h);
+    HIPCHECK(h, timed(h, XY_K_BONDS, [&] { return xy::launch_bonds(lc, false, h->stream); }));
+    HIPCHECK(h, timed(h, XY_K_MERGE, [&] { return xy::launch_merge(lc, true, h->stream); }));
+    HIPCHECK(h, timed(h, XY_K_FLIP, [&] { return xy::launch_flip(lc, fa, h->stream); }));
+    return XY_OK;
+}
+
+xy::FlipArgs no_pcc(const xy_handle *h)
+{
+    xy::FlipArgs fa;
+    std::memset(&fa, 0, sizeof fa);
+    fa.nrep = h->plan.n;
+    return fa;
+}
+
+int read_state(xy_handle *h, int32_t rep, xy::RepState *out)
+{
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipMemcpy(out, h->d_state + rep, sizeof *out, hipMemcpyDeviceToHost));
+    return XY_OK;
+}
+
+int check_rep(xy_handle *h, int32_t rep)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (rep < 0 || rep >= h->plan.n) return fail(XY_EINVAL, "replica %d outside [0, %d)", rep, h->plan.n);
+    return XY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *xy_last_error(void) { return g_err.c_str(); }
+
+int xy_bytes_required(const xy_params *p, int32_t n, size_t *bytes)
+{
+    if (!bytes) return fail(XY_EINVAL, "bytes pointer is NULL");
+    Plan P;
+    int rc = make_plan(p, n, P);
+    if (rc) return rc;
+    *bytes = P.total;
+    return XY_OK;
+}
+
+int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_t arena_bytes,
+             xy_handle **out)
+{
+    if (!out) return fail(XY_EINVAL, "out pointer is NULL");
+    *out = nullptr;
+    xy_handle *h = new (std::nothrow) xy_handle;
+    if (!h) return fail(XY_ENOMEM, "host allocation failed");
+    int rc = make_plan(p, n, h->plan);
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    const Plan &P = h->plan;
+    if (arena) {
+        if (arena_bytes < P.total) {
+            delete h;
+            return fail(XY_ENOMEM, "arena of %zu bytes is smaller than the %zu required", arena_bytes, P.total);
+        }
+        if (reinterpret_cast<uintptr_t>(arena) % kAlign) {
+            delete h;
+            return fail(XY_EINVAL, "arena is not %zu-byte aligned", kAlign);
+        }
+        h->arena = static_cast<char *>(arena);
+    } else {
+        void *mem = nullptr;
+        hipError_t e = hipMalloc(&mem, P.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete h;
+            return fail(XY_ENOMEM, "hipMalloc of %zu bytes failed: %s", P.total, hipGetErrorString(e));
+        }
+        h->arena = static_cast<char *>(mem);
+        h->own_arena = true;
+    }
+    if (hip_stream) {
+        h->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            xy_free(h);
+            return fail(XY_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+        }
+        h->own_stream = true;
+    }
+    char *A = h->arena;
+    h->d_reps = reinterpret_cast<xy::RepDesc *>(A + P.off_reps);
+    h->d_state = reinterpret_cast<xy::RepState *>(A + P.off_state);
+    h->d_tile_rep = n > 1 ? reinterpret_cast<uint32_t *>(A + P.off_tile_rep) : nullptr;
+    h->d_trace = reinterpret_cast<xy_obs *>(A + P.off_obs);
+    h->d_wmean = h->d_trace + kTraceChunk * n;
+    h->d_meas = h->d_wmean + kTraceChunk * n;
+    h->reps.resize(n);
+    std::vector<xy::RepState> states(n);
+    std::vector<uint32_t> tile_rep;
+    if (n > 1) tile_rep.resize(P.total_tiles);
+    int64_t base = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const Resolved &r = P.res[k];
+        const RepLayout &l = P.lay[k];
+        xy::RepDesc &d = h->reps[k];
+        std::memset(&d, 0, sizeof d);
+        d.c = reinterpret_cast<float *>(A + l.c);
+        d.s = reinterpret_cast<float *>(A + l.s);
+        for (int q = 0; q < 2; ++q) {
+            d.lab[q] = A + l.lab[q];
+            d.bx[q] = reinterpret_cast<uint32_t *>(A + l.bx[q]);
+            d.by[q] = reinterpret_cast<uint32_t *>(A + l.by[q]);
+            d.edge[q] = reinterpret_cast<float2 *>(A + l.edge[q]);
+        }
+        d.coins = reinterpret_cast<uint32_t *>(A + l.coins);
+        d.partials = reinterpret_cast<double *>(A + l.partials);
+        d.st = h->d_state + k;
+        d.L = r.L;
+        d.N = r.N;
+        d.ntiles = r.ntiles;
+        d.tile_base = base;
+        d.seed = p[k].seed;
+        d.rep = p[k].replica;
+        d.log2L = ilog2(r.L);
+        d.TW = r.TW;
+        d.TH = r.TH;
+        d.log2TW = ilog2(r.TW);
+        d.ntx = r.ntx;
+        d.nty = r.nty;
+        d.idx = k;
+        for (int64_t tt = 0; tt < r.ntiles && n > 1; ++tt) tile_rep[base + tt] = (uint32_t)k;
+        base += r.ntiles;
+        xy::RepState &s = states[k];
+        std::memset(&s, 0, sizeof s);
+        s.beta = p[k].beta;
+    }
+    HIPCHECK(h, hipMemcpy(h->d_reps, h->reps.data(), n * sizeof(xy::RepDesc), hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpy(h->d_state, states.data(), n * sizeof(xy::RepState), hipMemcpyHostToDevice));
+    if (n > 1)
+        HIPCHECK(h, hipMemcpy(h->d_tile_rep, tile_rep.data(), tile_rep.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice));
+    for (int32_t k = 0; k < n; ++k)
+        HIPCHECK(h, xy::launch_init_spins(h->d_reps, k, P.res[k].N, p[k].start, h->stream));
+    HIPCHECK(h, xy::launch_init_dir(h->d_reps, n, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    *out = h;
+    return XY_OK;
+}
+
+int xy_free(xy_handle *h)
+{
+    if (!h) return XY_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto &e : h->ev_used) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (auto &e : h->ev_free) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    if (h->own_arena && h->arena) (void)hipFree(h->arena);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return XY_OK;
+}
+
+int xy_sweep(xy_handle *h, int64_t nsweeps, xy_obs *trace)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (nsweeps < 0) return fail(XY_EINVAL, "nsweeps=%lld is negative", (long long)nsweeps);
+    const int32_t n = h->plan.n;
+    for (int64_t k = 0; k < nsweeps; ++k) {
+        xy::FlipArgs fa = no_pcc(h);
+        if (trace) {
+            fa.trace = h->d_trace;
+            fa.trace_row = k % kTraceChunk;
+        }
+        rc = enqueue_sweep(h, fa);
+        if (rc) return rc;
+        if (trace && (fa.trace_row == kTraceChunk - 1 || k == nsweeps - 1)) {
+            const int64_t first = k - fa.trace_row;
+            HIPCHECK(h, hipMemcpyAsync(trace + first * n, h->d_trace, (fa.trace_row + 1) * n * sizeof(xy_obs),
+                                       hipMemcpyDeviceToHost, h->stream));
+            HIPCHECK(h, hipStreamSynchronize(h->stream));
+        }
+    }
+    return XY_OK;
+}
+
+int xy_measure(xy_handle *h, xy_obs *out)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!out) return fail(XY_EINVAL, "out pointer is NULL");
+    const xy::Launch lc = launch_all(h);
+    HIPCHECK(h, xy::launch_measure(lc, h->d_meas, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(out, h->d_meas, h->plan.n * sizeof(xy_obs), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return XY_OK;
+}
+
+int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_mean)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!c) return fail(XY_EINVAL, "pcc pointer is NULL");
+    if (nsteps < 1) return fail(XY_EINVAL, "nsteps=%lld < 1", (long long)nsteps);
+    if (c->window < 1) return fail(XY_EINVAL, "window=%lld < 1", (long long)c->window);
+    if (!(c->dbeta0 > 0.0) || !(c->dbeta_min >= 0.0) || c->halve_every < 0 || !std::isfinite(c->target))
+        return fail(XY_EINVAL, "bad PCC schedule (dbeta0=%g dbeta_min=%g halve_every=%lld target=%g)",
+                    c->dbeta0, c->dbeta_min, (long long)c->halve_every, c->target);
+    const int32_t n = h->plan.n;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        for (int64_t w = 0; w < c->window; ++w) {
+            xy::FlipArgs fa = no_pcc(h);
+            fa.window = c->window;
+            fa.dbeta0 = c->dbeta0;
+            fa.dbeta_min = c->dbeta_min;
+            fa.halve_every = c->halve_every;
+            fa.target = c->target;
+            if (window_mean) {
+                fa.wmean = h->d_wmean;
+                fa.wrow = k % kTraceChunk;
+            }
+            rc = enqueue_sweep(h, fa);
+            if (rc) return rc;
+        }
+        const int64_t row = k % kTraceChunk;
+        if (window_mean && (row == kTraceChunk - 1 || k == nsteps - 1)) {
+            const int64_t first = k - row;
+            HIPCHECK(h, hipMemcpyAsync(window_mean + first * n, h->d_wmean, (row + 1) * n * sizeof(xy_obs),
+                                       hipMemcpyDeviceToHost, h->stream));
+            HIPCHECK(h, hipStreamSynchronize(h->stream));
+        }
+    }
+    return XY_OK;
+}
+
+int xy_get_state(xy_handle *h, int32_t rep, float *cos_out, float *sin_out)
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    if (!cos_out || !sin_out) return fail(XY_EINVAL, "output pointer is NULL");
+    const xy::RepDesc &d = h->reps[rep];
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipMemcpy(cos_out, d.c, d.N * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHECK(h, hipMemcpy(sin_out, d.s, d.N * sizeof(float), hipMemcpyDeviceToHost));
+    return XY_OK;
+}
+
+int xy_set_state(xy_handle *h, int32_t rep, const float *cos_in, const float *sin_in)
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    if (!cos_in || !sin_in) return fail(XY_EINVAL, "input pointer is NULL");
+    const xy::RepDesc &d = h->reps[rep];
+    for (int64_t i = 0; i < d.N; ++i) {
+        const double n2 = (double)cos_in[i] * cos_in[i] + (double)sin_in[i] * sin_in[i];
+        if (!(std::fabs(n2 - 1.0) <= 1e-3))
+            return fail(XY_EINVAL, "spin %lld has squared length %g, not 1", (long long)i, n2);
+    }
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipMemcpy(d.c, cos_in, d.N * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpy(d.s, sin_in, d.N * sizeof(float), hipMemcpyHostToDevice));
+    return XY_OK;
+}
+
+int xy_get_labels(xy_handle *h, int32_t rep, int64_t *out)
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    if (!out) return fail(XY_EINVAL, "output pointer is NULL");
+    xy::RepState s;
+    rc = read_state(h, rep, &s);
+    if (rc) return rc;
+    if (s.t == 0) return fail(XY_ESTATE, "replica %d has not swept yet", rep);
+    const xy::RepDesc &d = h->reps[rep];
+    void *tmp = nullptr;
+    HIPCHECK(h, hipMalloc(&tmp, d.N * sizeof(int64_t)));
+    hipError_t e = xy::launch_flatten(d.lab[(s.t - 1) & 1], h->plan.label_bits, d.N, tmp, 64, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(out, tmp, d.N * sizeof(int64_t), hipMemcpyDeviceToHost);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(h, e, "label flatten");
+    return XY_OK;
+}
+
+int xy_get_bonds(xy_handle *h, int32_t rep, uint32_t *bx, uint32_t *by)
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    if (!bx || !by) return fail(XY_EINVAL, "output pointer is NULL");
+    xy::RepState s;
+    rc = read_state(h, rep, &s);
+    if (rc) return rc;
+    if (s.t == 0) return fail(XY_ESTATE, "replica %d has not swept yet", rep);
+    const xy::RepDesc &d = h->reps[rep];
+    const size_t words = (size_t)std::max<int64_t>(1, (d.N + 31) / 32);
+    HIPCHECK(h, hipMemcpy(bx, d.bx[(s.t - 1) & 1], words * 4, hipMemcpyDeviceToHost));
+    HIPCHECK(h, hipMemcpy(by, d.by[(s.t - 1) & 1], words * 4, hipMemcpyDeviceToHost));
+    return XY_OK;
+}
+
+int xy_set_beta(xy_handle *h, int32_t rep, double beta)
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    if (!(beta >= 0.0 && beta <= 1e4)) return fail(XY_EINVAL, "beta=%g outside [0, 1e4]", beta);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipMemcpy(&h->d_state[rep].beta, &beta, sizeof beta, hipMemcpyHostToDevice));
+    return XY_OK;
+}
+
+int xy_get_beta(xy_handle *h, int32_t rep, double *beta)
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    if (!beta) return fail(XY_EINVAL, "output pointer is NULL");
+    xy::RepState s;
+    rc = read_state(h, rep, &s);
+    if (rc) return rc;
+    *beta = s.beta;
+    return XY_OK;
+}
+
+int xy_get_sweep(xy_handle *h, int32_t rep, uint64_t *sweep, double r[2])
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    xy::RepState s;
+    rc = read_state(h, rep, &s);
+    if (rc) return rc;
+    if (sweep) *sweep = s.t;
+    if (r) {
+        r[0] = s.dir[s.t & 1][0];
+        r[1] = s.dir[s.t & 1][1];
+    }
+    return XY_OK;
+}
+
+int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint32_t *d_bx, const uint32_t *d_by,
+                   void *d_labels, void *hip_stream)
+{
+    xy_params p;
+    std::memset(&p, 0, sizeof p);
+    p.L = L;
+    p.label_bits = label_bits;
+    p.tile_rows = tile_rows;
+    if (!d_bx || !d_by || !d_labels) return fail(XY_EINVAL, "device pointer is NULL");
+    if (label_bits != 32 && label_bits != 64) return fail(XY_EINVAL, "label_bits=%d is not 32 or 64", label_bits);
+    Plan P;
+    int rc = make_plan(&p, 1, P);
+    if (rc) return rc;
+    const Resolved &r = P.res[0];
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    xy::RepDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.lab[0] = d.lab[1] = d_labels;
+    d.bx[0] = d.bx[1] = const_cast<uint32_t *>(d_bx);
+    d.by[0] = d.by[1] = const_cast<uint32_t *>(d_by);
+    d.L = r.L;
+    d.N = r.N;
+    d.ntiles = r.ntiles;
+    d.log2L = ilog2(r.L);
+    d.TW = r.TW;
+    d.TH = r.TH;
+    d.log2TW = ilog2(r.TW);
+    d.ntx = r.ntx;
+    d.nty = r.nty;
+    xy::RepState st;
+    std::memset(&st, 0, sizeof st);
+    char *mem = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&mem), 1024 + sizeof d + sizeof st);
+    if (e != hipSuccess) return fail(XY_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    xy::RepState *d_st = reinterpret_cast<xy::RepState *>(mem);
+    xy::RepDesc *d_rep = reinterpret_cast<xy::RepDesc *>(mem + 512);
+    d.st = d_st;
+    e = hipMemcpy(d_st, &st, sizeof st, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_rep, &d, sizeof d, hipMemcpyHostToDevice);
+    xy::Launch lc;
+    lc.reps = d_rep;
+    lc.tile_rep = nullptr;
+    lc.nrep = 1;
+    lc.label_bits = label_bits;
+    lc.max_th = r.TH;
+    lc.gtile0 = 0;
+    lc.gtile_end = r.ntiles;
+    if (e == hipSuccess) e = xy::launch_bonds(lc, true, s);
+    if (e == hipSuccess) e = xy::launch_merge(lc, false, s);
+    if (e == hipSuccess) e = xy::launch_flatten(d_labels, label_bits, r.N, d_labels, label_bits, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(mem);
+    if (e != hipSuccess) return fail(XY_EDEVICE, "labelling failed: %s", hipGetErrorString(e));
+    return XY_OK;
+}
+
+int xy_timing(xy_handle *h, int32_t enable)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    h->timing = enable != 0;
+    return XY_OK;
+}
+
+int xy_timing_read(xy_handle *h, double *ms, int64_t *launches)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    for (auto &e : h->ev_used) {
+        float t = 0.f;
+        HIPCHECK(h, hipEventElapsedTime(&t, e.a, e.b));
+        h->ms[e.kind] += t;
+        h->launches[e.kind] += 1;
+        h->ev_free.push_back(e);
+    }
+    h->ev_used.clear();
+    for (int k = 0; k < XY_K_COUNT; ++k) {
+        if (ms) ms[k] = h->ms[k];
+        if (launches) launches[k] = h->launches[k];
+        h->ms[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    return XY_OK;
+}
+
+}  // extern "C"

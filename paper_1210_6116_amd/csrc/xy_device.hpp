@@ -1,0 +1,131 @@
+// xy_device.hpp -- device-side building blocks of the MI355X Swendsen-Wang /
+// PCC engine for the 2D classical XY model (Komura & Okabe, arXiv:1210.6116):
+// the counter-based random stream, the per-replica descriptors shared by every
+// kernel, and the lattice geometry of a labelling tile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/xy.h"
+
+namespace xy {
+
+// ---------------------------------------------------------------------------
+// Random stream: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Every
+// number the sweep draws is a pure function of (seed, counter), so a replica's
+// trajectory does not depend on launch shape, batching or tile size.
+// Counter layout (word0, word1 = replica, word2, word3 = tag):
+//   BOND (pair = (y>>1)*L + x, rep, t, 1): words 0,1 = x-link, y-link of site
+//        (x, 2*(y>>1)); words 2,3 the same for site (x, 2*(y>>1)+1)
+//   FLIP (root>>7, rep, t, 2): coin of cluster root r = bit (r&31) of word (r>>5)&3
+//   DIR  (k, rep, t, 3), INIT (site, rep, k, 4): k-th attempt of a rejection
+//        draw of a point in the unit disk
+// ---------------------------------------------------------------------------
+enum : uint32_t { TAG_BOND = 1u, TAG_FLIP = 2u, TAG_DIR = 3u, TAG_INIT = 4u };
+constexpr int kMaxAttempts = 16;      // rejection draws (two candidates each)
+constexpr uint64_t kRenormEvery = 1024;  // spins rescaled to unit length after sweeps t with (t+1) % this == 0
+constexpr double kTieEps = 1e-9;         // |u - p| below this counts as a near tie
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ double unif64(uint32_t w) { return (double)w * (1.0 / 4294967296.0); }
+
+// ---------------------------------------------------------------------------
+// Replica descriptors.  A handle owns an array of RepDesc (read-only during a
+// sweep) and RepState (mutated on the device: beta, sweep counter, direction,
+// PCC window, reduction counters).
+// ---------------------------------------------------------------------------
+constexpr int kNumSums = 6;  // Scx, Ssx, Scy, Ssy, sum cos, sum sin
+
+struct RepState {
+    double beta;
+    uint64_t t;              // sweeps completed
+    double dir[2][2];        // mirror direction of sweep t in slot t&1
+    unsigned long long ties[2];  // near ties of sweep t in slot t&1
+    unsigned int done;       // tiles finished in the running reduction
+    unsigned int pad0;
+    double acc[8];           // PCC window sums: E, m2, ex, sx, ey, sy, ups_x, N sx^2
+    int64_t acc_n;           // sweeps in the running window
+    int64_t pcc_k;           // PCC steps taken (halving schedule)
+    uint64_t ties_total;
+    xy_obs last;             // observables after the latest sweep
+};
+
+struct RepDesc {
+    float *c, *s;            // spin planes, N floats each
+    void *lab[2];            // label forest of sweep t in slot t&1 (uint32 or uint64, N)
+    uint32_t *bx[2], *by[2]; // active-link bit planes of sweep t in slot t&1
+    uint32_t *coins;         // flip coins of sweep t, one bit per site
+    float2 *edge[2];         // per tile: pre-flip spins of its first column (TH) then first row (TW)
+    double *partials;        // per tile: kNumSums partial sums
+    RepState *st;
+    int64_t L, N;
+    int64_t ntiles, tile_base;  // tiles of this replica, first global tile id
+    uint64_t seed;
+    uint32_t rep;
+    int32_t log2L, TW, TH, log2TW, ntx, nty;
+    int32_t idx;             // position of the replica in its handle
+};
+
+// Tile geometry: TW = min(L, 64) columns (one wave64 lane per column) by
+// TH rows; tile (tx, ty) covers columns tx*TW.. and rows ty*TH..
+struct Tile {
+    int64_t L;
+    int32_t log2L, TW, TH, log2TW, tx, ty, ntx, nty;
+    int64_t x0, y0;
+    __device__ __forceinline__ int64_t site(int32_t ly, int32_t lx) const
+    {
+        return ((y0 + ly) << log2L) + x0 + lx;
+    }
+    __device__ __forceinline__ bool contains(uint64_t i) const
+    {
+        const int64_t y = (int64_t)(i >> log2L), x = (int64_t)(i & (uint64_t)(L - 1));
+        return y >= y0 && y < y0 + TH && x >= x0 && x < x0 + TW;
+    }
+    __device__ __forceinline__ int32_t local(uint64_t i) const
+    {
+        const int64_t y = (int64_t)(i >> log2L), x = (int64_t)(i & (uint64_t)(L - 1));
+        return (int32_t)(((y - y0) << log2TW) + (x - x0));
+    }
+};
+
+__device__ __forceinline__ Tile make_tile(const RepDesc &R, int64_t lt)
+{
+    Tile T;
+    T.L = R.L;
+    T.log2L = R.log2L;
+    T.TW = R.TW;
+    T.TH = R.TH;
+    T.log2TW = R.log2TW;
+    T.ntx = R.ntx;
+    T.nty = R.nty;
+    T.tx = (int32_t)(lt % R.ntx);
+    T.ty = (int32_t)(lt / R.ntx);
+    T.x0 = (int64_t)T.tx * R.TW;
+    T.y0 = (int64_t)T.ty * R.TH;
+    return T;
+}
+
+}  // namespace xy

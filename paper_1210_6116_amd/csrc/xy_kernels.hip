@@ -1,0 +1,870 @@
+// xy_kernels.hip -- gfx950 kernels of one Swendsen-Wang sweep of the 2D
+// classical XY model with Wolff's embedded-cluster formalism, the fused
+// observable reductions, and the generalized PCC beta step (Komura & Okabe,
+// arXiv:1210.6116: Eq. (Hc); the SW / PCC paragraphs; the helicity-modulus
+// definitions of e and s; the simulation paragraph for the PCC parameters).
+//
+// A sweep is three launches over 64-column tiles (one wave64 lane per column):
+//   k_bonds_ccl : mirror-direction projection, link activation (bit planes),
+//                 in-tile union-find in LDS (row runs from wave ballots, then
+//                 vertical unions), tile-local labels, flip-coin table
+//   k_merge     : union of the labels across every active link that leaves a
+//                 tile (lock-free, the larger root always hooked under the
+//                 smaller one, so every final root is its cluster's minimum site)
+//   k_flip      : root lookup, reflection of flipped clusters in FP64 with one
+//                 rounding to the FP32 state, the six link / site sums of the
+//                 flipped state, and (in the last tile of each replica) the
+//                 observables, the PCC window and the sweep counter
+// Built with -ffp-contract=off: the FP64 expressions below are evaluated
+// operation by operation, exactly as written.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xy_device.hpp"
+#include "xy_launch.hpp"
+
+namespace xy {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ const RepDesc &rep_of(const RepDesc *__restrict__ reps,
+                                                 const uint32_t *__restrict__ tile_rep,
+                                                 int32_t nrep, int64_t gtile, int64_t &lt)
+{
+    const RepDesc &R = reps[nrep == 1 ? 0 : tile_rep[gtile]];
+    lt = gtile - R.tile_base;
+    return R;
+}
+
+__device__ __forceinline__ int band_rows(int TH) { return TH >= kWaves ? TH / kWaves : 1; }
+
+// Point on the unit circle: a uniform point of the unit disk by rejection from
+// [-1,1]^2, scaled to unit length (only correctly rounded FP64 operations).
+__device__ void disk_point(uint64_t seed, uint32_t rep, uint32_t tag, uint32_t idx, uint32_t tword,
+                           bool attempts_in_word0, double *ox, double *oy)
+{
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (uint32_t k = 0; k < (uint32_t)kMaxAttempts; ++k) {
+        const U4 w = attempts_in_word0 ? philox4x32_10(k, rep, tword, tag, k0, k1)
+                                       : philox4x32_10(idx, rep, k, tag, k0, k1);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+        for (int pair = 0; pair < 2; ++pair) {
+            const double vx = 2.0 * unif64(ws[2 * pair]) - 1.0;
+            const double vy = 2.0 * unif64(ws[2 * pair + 1]) - 1.0;
+            const double q = vx * vx + vy * vy;
+            if (q > 0.0 && q < 1.0) {
+                const double n = sqrt(q);
+                *ox = vx / n;
+                *oy = vy / n;
+                return;
+            }
+        }
+    }
+    *ox = 1.0;
+    *oy = 0.0;
+}
+
+__device__ __forceinline__ void compute_direction(const RepDesc &R, uint64_t t)
+{
+    double rx, ry;
+    disk_point(R.seed, R.rep, TAG_DIR, 0u, (uint32_t)t, true, &rx, &ry);
+    R.st->dir[t & 1][0] = rx;
+    R.st->dir[t & 1][1] = ry;
+}
+
+// Exact (FP64) link decision, identical operation order to the definition:
+// a = c rx + s ry; x = ((2 beta) a_i) a_j; active iff x > 0 and exp(-x) < 1 - u.
+__device__ __noinline__ bool bond_exact(const float *__restrict__ c, const float *__restrict__ s,
+                                        int64_t i, int64_t j, double rx, double ry, double beta,
+                                        uint32_t w, unsigned long long *ties)
+{
+    const double ci = c[i], si = s[i], cj = c[j], sj = s[j];
+    const double ai = ci * rx + si * ry;
+    const double aj = cj * rx + sj * ry;
+    const double xb = ((2.0 * beta) * ai) * aj;
+    const double e = (xb > 0.0) ? exp(-xb) : 1.0;
+    const double omu = 1.0 - unif64(w);
+    if (fabs(e - omu) < kTieEps) atomicAdd(ties, 1ull);
+    return e < omu;
+}
+
+// FP32 decision with a guard band: the FP32 value of exp(-x) is within
+// ~1e-6 (1 + beta) of the FP64 one for unit spins, so outside |e - (1-u)| <= G
+// both precisions agree; inside it the FP64 decision is taken.
+struct BondCtx {
+    const float *c, *s;
+    double rx, ry, beta;
+    float b2f, guard;
+    unsigned long long *ties;
+};
+
+__device__ __forceinline__ bool bond_decide(const BondCtx &B, float ai, float aj, uint32_t w,
+                                            int64_t i, int64_t j)
+{
+    const float xb = (B.b2f * ai) * aj;
+    const float e = xb > 0.0f ? __expf(-xb) : 1.0f;
+    const float omu = 1.0f - (float)w * 2.3283064365386963e-10f;
+    if (fabsf(e - omu) <= B.guard) return bond_exact(B.c, B.s, i, j, B.rx, B.ry, B.beta, w, B.ties);
+    return e < omu;
+}
+
+// ------------------------------------------------------- union-find in LDS
+__device__ __forceinline__ uint32_t lds_load(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t find_lds(const uint32_t *lab, uint32_t x)
+{
+    while (true) {
+        const uint32_t p = lds_load(&lab[x]);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+__device__ void union_lds(uint32_t *lab, uint32_t a, uint32_t b)
+{
+    while (true) {
+        a = find_lds(lab, a);
+        b = find_lds(lab, b);
+        if (a == b) return;
+        if (a > b) {
+            const uint32_t tmp = a;
+            a = b;
+            b = tmp;
+        }
+        const uint32_t old = atomicMin(&lab[b], a);
+        if (old == b) return;
+        b = old;  // b was hooked meanwhile: merge a with its new parent
+    }
+}
+
+// ------------------------------------------------- union-find in global memory
+template <typename LT>
+__device__ __forceinline__ LT gload(const LT *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename LT>
+__device__ LT find_global(const LT *lab, LT x)
+{
+    while (true) {
+        const LT p = gload(&lab[x]);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+template <typename LT>
+__device__ void union_global(LT *lab, LT a, LT b)
+{
+    while (true) {
+        a = find_global(lab, a);
+        b = find_global(lab, b);
+        if (a == b) return;
+        if (a > b) {
+            const LT tmp = a;
+            a = b;
+            b = tmp;
+        }
+        const LT old = atomicMin(&lab[b], a);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+// Root of x in a finished forest (no concurrent hooks); the path is then
+// pointed straight at the root.
+template <typename LT>
+__device__ LT find_compress(LT *lab, LT x)
+{
+    LT r = x;
+    while (true) {
+        const LT p = lab[r];
+        if (p == r) break;
+        r = p;
+    }
+    while (x != r) {
+        const LT p = lab[x];
+        if (p == r) break;
+        lab[x] = r;
+        x = p;
+    }
+    return r;
+}
+
+// --------------------------------------------------------------- init
+__global__ __launch_bounds__(kThreads) void k_init_spins(const RepDesc *__restrict__ reps, int32_t r,
+                                                          int32_t start)
+{
+    const RepDesc &R = reps[r];
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= R.N) return;
+    double x = 1.0, y = 0.0;
+    if (start == XY_START_HOT) disk_point(R.seed, R.rep, TAG_INIT, (uint32_t)i, 0u, false, &x, &y);
+    R.c[i] = (float)x;
+    R.s[i] = (float)y;
+}
+
+__global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    compute_direction(reps[r], reps[r].st->t);
+}
+
+// ------------------------------------------------- K1: bonds + tile labelling
+// LDS: a[(TH+1)*(TW+1)] f32 | lab[TW*TH] u32 | bxm[TH], bym[TH] u64
+template <typename LT, bool FROM_PLANES>
+__global__ __launch_bounds__(kThreads) void k_bonds_ccl(const RepDesc *__restrict__ reps,
+                                                         const uint32_t *__restrict__ tile_rep,
+                                                         int32_t nrep, int64_t gtile0)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t lt;
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
+    const Tile T = make_tile(R, lt);
+    const int TW = T.TW, TH = T.TH, AS = TW + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int B = band_rows(TH), yb = wave * B;
+    const int64_t L = T.L, Lm = L - 1;
+    RepState *st = R.st;
+    const uint64_t t = st->t;
+    const int par = (int)(t & 1);
+
+    uint64_t *bxm = (uint64_t *)smem;
+    uint64_t *bym = bxm + 64;
+    uint32_t *lab_s = (uint32_t *)(bym + 64);
+    float *a_s = (float *)(lab_s + TW * TH);
+
+    if (!FROM_PLANES) {
+        const double rx = st->dir[par][0], ry = st->dir[par][1], beta = st->beta;
+        const float rxf = (float)rx, ryf = (float)ry;
+        const float *__restrict__ cp = R.c;
+        const float *__restrict__ sp = R.s;
+        // projections a = s . r of the tile, its right halo column and bottom halo row
+        for (int k = 0; k < B; ++k) {
+            const int y = yb + k;
+            if (y < TH && lane < TW) {
+                const int64_t i = T.site(y, lane);
+                a_s[y * AS + lane] = cp[i] * rxf + sp[i] * ryf;
+            }
+        }
+        float2 *edge = R.edge[par] + lt * (TH + TW);
+        if (wave == 0 && lane < TW) {
+            const int64_t i = (((T.y0 + TH) & Lm) << T.log2L) + T.x0 + lane;
+            a_s[TH * AS + lane] = cp[i] * rxf + sp[i] * ryf;
+        } else if (wave == 1 && lane < TH) {
+            const int64_t i = ((T.y0 + lane) << T.log2L) + ((T.x0 + TW) & Lm);
+            a_s[lane * AS + TW] = cp[i] * rxf + sp[i] * ryf;
+        } else if (wave == 2 && lane < TH) {
+            const int64_t i = T.site(lane, 0);  // first column, seen as halo by the left tile
+            edge[lane] = make_float2(cp[i], sp[i]);
+        } else if (wave == 3 && lane < TW) {
+            const int64_t i = T.site(0, lane);  // first row, seen as halo by the upper tile
+            edge[TH + lane] = make_float2(cp[i], sp[i]);
+        }
+        __syncthreads();
+
+        BondCtx ctx;
+        ctx.c = cp;
+        ctx.s = sp;
+        ctx.rx = rx;
+        ctx.ry = ry;
+        ctx.beta = beta;
+        ctx.b2f = (float)(2.0 * beta);
+        ctx.guard = 1e-5f * (1.0f + (float)beta);
+        ctx.ties = &st->ties[par];
+        const uint32_t key0 = (uint32_t)R.seed, key1 = (uint32_t)(R.seed >> 32);
+        U4 w = {0u, 0u, 0u, 0u};
+        for (int k = 0; k < B; ++k) {
+            const int y = yb + k;
+            if (y >= TH) break;
+            const int64_t gy = T.y0 + y;
+            bool xa = false, ya = false;
+            if (lane < TW) {
+                const int64_t gx = T.x0 + lane;
+                if (k == 0 || (gy & 1) == 0)
+                    w = philox4x32_10((uint32_t)(((gy >> 1) << T.log2L) + gx), R.rep, (uint32_t)t,
+                                      TAG_BOND, key0, key1);
+                const uint32_t wx = (gy & 1) ? w.z : w.x;
+                const uint32_t wy = (gy & 1) ? w.w : w.y;
+                const int64_t i = (gy << T.log2L) + gx;
+                const float ai = a_s[y * AS + lane];
+                xa = bond_decide(ctx, ai, a_s[y * AS + lane + 1], wx, i,
+                                 (gy << T.log2L) + ((gx + 1) & Lm));
+                ya = bond_decide(ctx, ai, a_s[(y + 1) * AS + lane], wy, i,
+                                 (((gy + 1) & Lm) << T.log2L) + gx);
+            }
+            const uint64_t mx = __ballot(xa), my = __ballot(ya);
+            if (lane == 0) {
+                bxm[y] = mx;
+                bym[y] = my;
+            }
+        }
+        __syncthreads();
+        // active-link bit planes of this sweep
+        uint32_t *gbx = R.bx[par], *gby = R.by[par];
+        if (TW == 64) {
+            for (int j = threadIdx.x; j < 2 * TH; j += kThreads) {
+                const int y = j >> 1, half = j & 1;
+                const int64_t word = (T.site(y, 0) >> 5) + half;
+                gbx[word] = (uint32_t)(bxm[y] >> (32 * half));
+                gby[word] = (uint32_t)(bym[y] >> (32 * half));
+            }
+        } else {
+            // narrow lattice (L < 64): the tile spans whole rows, so whole words
+            const int nbits = TW * TH;
+            const int nwords = nbits >= 32 ? nbits >> 5 : 1;
+            for (int j = threadIdx.x; j < nwords; j += kThreads) {
+                uint32_t vx = 0u, vy = 0u;
+                for (int b = 0; b < 32; ++b) {
+                    const int p = j * 32 + b;
+                    if (p >= nbits) break;
+                    const int y = p >> T.log2TW, x = p & (TW - 1);
+                    vx |= (uint32_t)((bxm[y] >> x) & 1ull) << b;
+                    vy |= (uint32_t)((bym[y] >> x) & 1ull) << b;
+                }
+                const int64_t word = (T.site(0, 0) >> 5) + j;
+                gbx[word] = vx;
+                gby[word] = vy;
+            }
+        }
+        // flip-coin table of this sweep: this tile's share of the N/128 blocks
+        const int64_t N = R.N;
+        if (N >= 128) {
+            const int nc = (TW * TH) >> 7;
+            for (int j = threadIdx.x; j < nc; j += kThreads) {
+                const int64_t cb = lt * nc + j;
+                const U4 o = philox4x32_10((uint32_t)cb, R.rep, (uint32_t)t, TAG_FLIP, key0, key1);
+                uint4 *dst = (uint4 *)(R.coins + cb * 4);
+                *dst = make_uint4(o.x, o.y, o.z, o.w);
+            }
+        } else if (lt == 0 && threadIdx.x == 0) {
+            const U4 o = philox4x32_10(0u, R.rep, (uint32_t)t, TAG_FLIP, key0, key1);
+            R.coins[0] = o.x;
+            R.coins[1] = o.y;
+            R.coins[2] = o.z;
+            R.coins[3] = o.w;
+        }
+    } else {
+        // given link planes (standalone labelling): gather this tile's row masks
+        const uint32_t *gbx = R.bx[par], *gby = R.by[par];
+        for (int y = threadIdx.x; y < TH; y += kThreads) {
+            uint64_t mx = 0, my = 0;
+            for (int x = 0; x < TW; ++x) {
+                const int64_t i = T.site(y, x);
+                mx |= (uint64_t)((gbx[i >> 5] >> (i & 31)) & 1u) << x;
+                my |= (uint64_t)((gby[i >> 5] >> (i & 31)) & 1u) << x;
+            }
+            bxm[y] = mx;
+            bym[y] = my;
+        }
+        __syncthreads();
+    }
+
+    // ---- in-tile labelling
+    const uint64_t twmask = TW == 64 ? ~0ull : ((1ull << TW) - 1ull);
+    const uint64_t inner = twmask >> 1;  // link x -> x+1 stays inside the tile
+    // 1) row runs: each site points at the first site of its run of x-links
+    for (int k = 0; k < B; ++k) {
+        const int y = yb + k;
+        if (y < TH && lane < TW) {
+            const uint64_t breaks = ~(bxm[y] & inner) & ((1ull << lane) - 1ull);
+            const int start = breaks ? 64 - __clzll((long long)breaks) : 0;
+            lab_s[y * TW + lane] = (uint32_t)(y * TW + start);
+        }
+    }
+    __syncthreads();
+    // 2) vertical links inside the tile; a link whose left neighbour joins the
+    //    same two runs is skipped
+    for (int k = 0; k < B; ++k) {
+        const int y = yb + k;
+        if (y < TH - 1 && lane < TW) {
+            const uint64_t v = bym[y] & twmask;
+            const uint64_t h0 = bxm[y] & inner, h1 = bxm[y + 1] & inner;
+            const uint64_t need = v & ~(v & (v << 1) & (h0 << 1) & (h1 << 1));
+            if ((need >> lane) & 1ull) union_lds(lab_s, (uint32_t)(y * TW + lane), (uint32_t)((y + 1) * TW + lane));
+        }
+    }
+    __syncthreads();
+    // 3) tile-local roots as global site indices
+    LT *lab = (LT *)R.lab[par];
+    for (int k = 0; k < B; ++k) {
+        const int y = yb + k;
+        if (y < TH && lane < TW) {
+            const uint32_t r = find_lds(lab_s, (uint32_t)(y * TW + lane));
+            lab[T.site(y, lane)] = (LT)T.site((int)(r >> T.log2TW), (int)(r & (TW - 1)));
+        }
+    }
+}
+
+// ------------------------------------------------- K2: merge across tiles
+// One wave per (tile, edge): edge 0 = links leaving the right column, edge 1 =
+// links leaving the bottom row.
+template <typename LT>
+__global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ reps,
+                                                     const uint32_t *__restrict__ tile_rep,
+                                                     int32_t nrep, int64_t gtile0, int64_t gtile_end,
+                                                     int32_t next_dir)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
+    const int64_t gtile = gtile0 + (gw >> 1);
+    const int edge = (int)(gw & 1);
+    if (gtile >= gtile_end) return;
+    int64_t lt;
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
+    const Tile T = make_tile(R, lt);
+    const int64_t Lm = T.L - 1;
+    const uint64_t t = R.st->t;
+    const int par = (int)(t & 1);
+    LT *lab = (LT *)R.lab[par];
+    bool on = false;
+    int64_t i = 0, j = 0;
+    if (edge == 0) {
+        if (lane < T.TH) {
+            const int64_t gy = T.y0 + lane, gx = T.x0 + T.TW - 1;
+            i = (gy << T.log2L) + gx;
+            on = (R.bx[par][i >> 5] >> (i & 31)) & 1u;
+            j = (gy << T.log2L) + ((gx + 1) & Lm);
+        }
+    } else {
+        if (lane < T.TW) {
+            const int64_t gy = T.y0 + T.TH - 1, gx = T.x0 + lane;
+            i = (gy << T.log2L) + gx;
+            on = (R.by[par][i >> 5] >> (i & 31)) & 1u;
+            j = (((gy + 1) & Lm) << T.log2L) + gx;
+        }
+    }
+    LT a = 0, b = 0;
+    if (on) {
+        a = lab[i];
+        b = lab[j];
+    }
+    const LT pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
+    const int pon = __shfl_up((int)on, 1);
+    const bool dup = lane > 0 && pon && pa == a && pb == b;
+    if (on && !dup) union_global(lab, a, b);
+    if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
+}
+
+// --------------------------------------------- reductions (fixed order)
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double *red /* kWaves*K */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = red[k];
+            for (int w2 = 1; w2 < kWaves; ++w2) s += red[w2 * K + k];
+            v[k] = s;
+        }
+    }
+}
+
+// Observables from the six sums (same formulas as the definitions): called by
+// one thread.
+__device__ __forceinline__ void obs_from_sums(const double *S, double N, double beta, xy_obs *o)
+{
+    o->E = -(S[0] + S[2]) / N;
+    o->m2 = (S[4] * S[4] + S[5] * S[5]) / (N * N);
+    o->ex = S[0] / N;
+    o->sx = S[1] / N;
+    o->ey = S[2] / N;
+    o->sy = S[3] / N;
+    o->ups_x = o->ex - beta * N * o->sx * o->sx;
+}
+
+// Last tile of a replica to finish: reduce the per-tile partial sums in a
+// fixed order.  Returns true in every thread of that block; the totals are in
+// tot[] of thread 0.
+__device__ bool last_tile_reduce(const RepDesc &R, int64_t lt, double (&v)[kNumSums], double *red,
+                                 double (&tot)[kNumSums])
+{
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+        double *dst = R.partials + lt * kNumSums;
+#pragma unroll
+        for (int k = 0; k < kNumSums; ++k) dst[k] = v[k];
+        __threadfence();
+        const unsigned prev = atomicAdd(&R.st->done, 1u);
+        is_last = (prev == (unsigned)(R.ntiles - 1));
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double s[kNumSums];
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) s[k] = 0.0;
+    for (int64_t j = threadIdx.x; j < R.ntiles; j += kThreads) {
+        const double *src = R.partials + j * kNumSums;
+#pragma unroll
+        for (int k = 0; k < kNumSums; ++k) s[k] += __builtin_nontemporal_load(const_cast<double *>(&src[k]));
+    }
+    __syncthreads();
+    block_sum<kNumSums>(s, red);
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) tot[k] = s[k];
+    return true;
+}
+
+// ------------------------------------------------- K3: flip + reductions
+// LDS: memo[TW*TH] LT | post-flip spins sp[(TH+1)*(TW+1)] float2 | red
+template <typename LT>
+__global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ reps,
+                                                    const uint32_t *__restrict__ tile_rep,
+                                                    int32_t nrep, int64_t gtile0, FlipArgs fa)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kWaves * kNumSums];
+    int64_t lt;
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
+    const Tile T = make_tile(R, lt);
+    const int TW = T.TW, TH = T.TH, SS = TW + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int B = band_rows(TH), yb = wave * B;
+    const int64_t Lm = T.L - 1;
+    RepState *st = R.st;
+    const uint64_t t = st->t;
+    const int par = (int)(t & 1);
+    const double rx = st->dir[par][0], ry = st->dir[par][1];
+    const bool renorm = ((t + 1) % kRenormEvery) == 0;
+    LT *lab = (LT *)R.lab[par];
+    const uint32_t *__restrict__ coins = R.coins;
+    float *__restrict__ cp = R.c;
+    float *__restrict__ sp = R.s;
+    const LT UNK = ~(LT)0;
+
+    LT *memo = (LT *)smem;
+    float2 *spin = (float2 *)(memo + TW * TH);
+
+    auto flip_one = [&](LT root, float c0, float s0, float &c1, float &s1) -> bool {
+        const bool f = (coins[root >> 5] >> (root & 31)) & 1u;
+        double c = c0, s = s0;
+        if (f) {
+            const double g = 2.0 * (c * rx + s * ry);
+            c = (double)(float)(c - g * rx);
+            s = (double)(float)(s - g * ry);
+        }
+        if (renorm) {
+            const double n = sqrt(c * c + s * s);
+            c = (double)(float)(c / n);
+            s = (double)(float)(s / n);
+        }
+        c1 = (float)c;
+        s1 = (float)s;
+        return f || renorm;
+    };
+
+    // Phase A: parents; roots of clusters that leave the tile are resolved now
+    for (int k = 0; k < B; ++k) {
+        const int y = yb + k;
+        if (y < TH && lane < TW) {
+            const int64_t i = T.site(y, lane);
+            const LT p = lab[i];
+            LT m = UNK;
+            if (p == (LT)i)
+                m = p;
+            else if (!T.contains((uint64_t)p))
+                m = find_compress(lab, p);
+            memo[y * TW + lane] = m;
+        }
+    }
+    // halo: right column and bottom row of the neighbouring tiles (pre-flip
+    // spins from their edge copies), flipped here as their owners flip them
+    if (wave == 0 && lane < TH) {
+        const int64_t h = ((T.y0 + lane) << T.log2L) + ((T.x0 + TW) & Lm);
+        const LT root = find_compress(lab, (LT)h);
+        const int64_t ltr = (int64_t)T.ty * T.ntx + (T.tx + 1) % T.ntx;
+        const float2 e = R.edge[par][ltr * (TH + TW) + lane];
+        float c1, s1;
+        flip_one(root, e.x, e.y, c1, s1);
+        spin[lane * SS + TW] = make_float2(c1, s1);
+    } else if (wave == 1 && lane < TW) {
+        const int64_t h = (((T.y0 + TH) & Lm) << T.log2L) + T.x0 + lane;
+        const LT root = find_compress(lab, (LT)h);
+        const int64_t ltd = (int64_t)((T.ty + 1) % T.nty) * T.ntx + T.tx;
+        const float2 e = R.edge[par][ltd * (TH + TW) + TH + lane];
+        float c1, s1;
+        flip_one(root, e.x, e.y, c1, s1);
+        spin[TH * SS + lane] = make_float2(c1, s1);
+    }
+    __syncthreads();
+
+    // Phase B: roots of the remaining sites via the tile memo, then the flip
+    for (int k = 0; k < B; ++k) {
+        const int y = yb + k;
+        if (y < TH && lane < TW) {
+            const int64_t i = T.site(y, lane);
+            LT root = memo[y * TW + lane];
+            if (root == UNK) {
+                LT x = lab[i];
+                while (true) {
+                    if (!T.contains((uint64_t)x)) {
+                        root = find_compress(lab, x);
+                        break;
+                    }
+                    const LT m = memo[T.local((uint64_t)x)];
+                    if (m != UNK) {
+                        root = m;
+                        break;
+                    }
+                    x = lab[x];
+                }
+            }
+            const float c0 = cp[i], s0 = sp[i];
+            float c1, s1;
+            if (flip_one(root, c0, s0, c1, s1)) {
+                cp[i] = c1;
+                sp[i] = s1;
+            }
+            spin[y * SS + lane] = make_float2(c1, s1);
+        }
+    }
+    __syncthreads();
+
+    // Phase C: link and site sums of the flipped configuration
+    double v[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < B; ++k) {
+        const int y = yb + k;
+        if (y < TH && lane < TW) {
+            const float2 a = spin[y * SS + lane];
+            const float2 r = spin[y * SS + lane + 1];
+            const float2 d = spin[(y + 1) * SS + lane];
+            const double ci = a.x, si = a.y, cr = r.x, sr = r.y, cd = d.x, sd = d.y;
+            v[0] += ci * cr + si * sr;
+            v[1] += si * cr - ci * sr;
+            v[2] += ci * cd + si * sd;
+            v[3] += si * cd - ci * sd;
+            v[4] += ci;
+            v[5] += si;
+        }
+    }
+    block_sum<kNumSums>(v, red);
+    double tot[kNumSums];
+    if (!last_tile_reduce(R, lt, v, red, tot)) return;
+    if (threadIdx.x != 0) return;
+
+    // Finalise the sweep: observables, PCC window, counters.
+    const double beta = st->beta;
+    const double N = (double)R.N;
+    xy_obs o;
+    o.sweep = t + 1;
+    o.beta = beta;
+    obs_from_sums(tot, N, beta, &o);
+    o.near_ties = st->ties[par];
+    st->ties_total += o.near_ties;
+    st->ties[par] = 0ull;
+    st->last = o;
+    if (fa.trace) fa.trace[fa.trace_row * fa.nrep + R.idx] = o;
+    if (fa.window > 0) {
+        double *acc = st->acc;
+        acc[0] += o.E;
+        acc[1] += o.m2;
+        acc[2] += o.ex;
+        acc[3] += o.sx;
+        acc[4] += o.ey;
+        acc[5] += o.sy;
+        acc[6] += o.ups_x;
+        acc[7] += N * o.sx * o.sx;
+        st->acc_n += 1;
+        if (st->acc_n >= fa.window) {
+            const double W = (double)fa.window;
+            const double mean_ex = acc[2] / W, mean_ns2 = acc[7] / W;
+            const double bu = beta * (mean_ex - beta * mean_ns2);
+            double db = fa.dbeta0;
+            if (fa.halve_every > 0) {
+                const int64_t halvings = st->pcc_k / fa.halve_every;
+                db = ldexp(fa.dbeta0, -(int)(halvings < 200 ? halvings : 200));
+            }
+            if (db < fa.dbeta_min) db = fa.dbeta_min;
+            const double nb = beta + ((bu < fa.target) ? db : -db);
+            if (fa.wmean) {
+                xy_obs m;
+                m.sweep = t + 1;
+                m.beta = nb;
+                m.E = acc[0] / W;
+                m.m2 = acc[1] / W;
+                m.ex = acc[2] / W;
+                m.sx = acc[3] / W;
+                m.ey = acc[4] / W;
+                m.sy = acc[5] / W;
+                m.ups_x = acc[6] / W;
+                m.near_ties = 0;
+                fa.wmean[fa.wrow * fa.nrep + R.idx] = m;
+            }
+            st->beta = nb;
+            st->pcc_k += 1;
+            for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+            st->acc_n = 0;
+        }
+    }
+    st->done = 0u;
+    st->t = t + 1;
+}
+
+// ------------------------------------------------- measure (no update)
+template <typename LT>
+__global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict__ reps,
+                                                       const uint32_t *__restrict__ tile_rep,
+                                                       int32_t nrep, int64_t gtile0, xy_obs *out)
+{
+    __shared__ double red[kWaves * kNumSums];
+    int64_t lt;
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
+    const Tile T = make_tile(R, lt);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int B = band_rows(T.TH), yb = wave * B;
+    const int64_t Lm = T.L - 1;
+    double v[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < B; ++k) {
+        const int y = yb + k;
+        if (y < T.TH && lane < T.TW) {
+            const int64_t gy = T.y0 + y, gx = T.x0 + lane;
+            const int64_t i = (gy << T.log2L) + gx;
+            const int64_t jr = (gy << T.log2L) + ((gx + 1) & Lm);
+            const int64_t jd = (((gy + 1) & Lm) << T.log2L) + gx;
+            const double ci = R.c[i], si = R.s[i], cr = R.c[jr], sr = R.s[jr], cd = R.c[jd], sd = R.s[jd];
+            v[0] += ci * cr + si * sr;
+            v[1] += si * cr - ci * sr;
+            v[2] += ci * cd + si * sd;
+            v[3] += si * cd - ci * sd;
+            v[4] += ci;
+            v[5] += si;
+        }
+    }
+    block_sum<kNumSums>(v, red);
+    double tot[kNumSums];
+    if (!last_tile_reduce(R, lt, v, red, tot)) return;
+    if (threadIdx.x != 0) return;
+    RepState *st = R.st;
+    xy_obs o;
+    o.sweep = st->t;
+    o.beta = st->beta;
+    obs_from_sums(tot, (double)R.N, st->beta, &o);
+    o.near_ties = 0;
+    out[R.idx] = o;
+    st->done = 0u;
+}
+
+// ------------------------------------------------- canonical labels
+template <typename LT>
+__global__ __launch_bounds__(kThreads) void k_flatten(const LT *__restrict__ lab, int64_t N, void *out,
+                                                       int32_t out_bits)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= N) return;
+    LT x = (LT)i;
+    while (true) {
+        const LT p = lab[x];
+        if (p == x) break;
+        x = p;
+    }
+    if (out_bits == 64)
+        ((uint64_t *)out)[i] = (uint64_t)x;
+    else
+        ((uint32_t *)out)[i] = (uint32_t)x;
+}
+
+// ====================================================== host-side launchers
+static size_t lds_bonds(int TH) { return 2 * 64 * sizeof(uint64_t) + 64 * TH * sizeof(uint32_t) + (TH + 1) * 65 * sizeof(float); }
+
+template <typename LT>
+static size_t lds_flip(int TH)
+{
+    return 64 * TH * sizeof(LT) + (TH + 1) * 65 * sizeof(float2);
+}
+
+hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s)
+{
+    const int64_t blocks = (N + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_init_spins, dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, start);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_dir, dim3((nrep + 63) / 64), dim3(64), 0, s, d_reps, nrep);
+    return hipGetLastError();
+}
+
+hipError_t launch_bonds(const Launch &lc, bool from_planes, hipStream_t s)
+{
+    const size_t lds = lds_bonds(lc.max_th);
+    const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
+    if (lc.label_bits == 64) {
+        if (from_planes)
+            hipLaunchKernelGGL((k_bonds_ccl<unsigned long long, true>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+        else
+            hipLaunchKernelGGL((k_bonds_ccl<unsigned long long, false>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+    } else {
+        if (from_planes)
+            hipLaunchKernelGGL((k_bonds_ccl<uint32_t, true>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+        else
+            hipLaunchKernelGGL((k_bonds_ccl<uint32_t, false>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s)
+{
+    const int64_t waves = 2 * (lc.gtile_end - lc.gtile0);
+    const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves)), block(kThreads);
+    if (lc.label_bits == 64)
+        hipLaunchKernelGGL((k_merge<unsigned long long>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
+    else
+        hipLaunchKernelGGL((k_merge<uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip(const Launch &lc, const FlipArgs &fa, hipStream_t s)
+{
+    const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
+    if (lc.label_bits == 64)
+        hipLaunchKernelGGL((k_flip<unsigned long long>), grid, block, lds_flip<unsigned long long>(lc.max_th), s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, fa);
+    else
+        hipLaunchKernelGGL((k_flip<uint32_t>), grid, block, lds_flip<uint32_t>(lc.max_th), s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, fa);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(const Launch &lc, xy_obs *d_out, hipStream_t s)
+{
+    const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
+    if (lc.label_bits == 64)
+        hipLaunchKernelGGL((k_measure<unsigned long long>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, d_out);
+    else
+        hipLaunchKernelGGL((k_measure<uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flatten(const void *d_lab, int32_t label_bits, int64_t N, void *d_out, int32_t out_bits,
+                          hipStream_t s)
+{
+    const int64_t blocks = (N + kThreads - 1) / kThreads;
+    if (label_bits == 64)
+        hipLaunchKernelGGL((k_flatten<unsigned long long>), dim3((unsigned)blocks), dim3(kThreads), 0, s, (const unsigned long long *)d_lab, N, d_out, out_bits);
+    else
+        hipLaunchKernelGGL((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, (const uint32_t *)d_lab, N, d_out, out_bits);
+    return hipGetLastError();
+}
+
+size_t lds_bytes_bonds(int TH) { return lds_bonds(TH); }
+size_t lds_bytes_flip(int TH, int label_bits) { return label_bits == 64 ? lds_flip<unsigned long long>(TH) : lds_flip<uint32_t>(TH); }
+
+}  // namespace xy

@@ -1,0 +1,48 @@
+// xy_launch.hpp -- host-side launchers of the sweep kernels (internal to libxy).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/xy.h"
+
+namespace xy {
+
+struct RepDesc;
+
+// One launch covers the global tiles [gtile0, gtile_end) of a handle.
+struct Launch {
+    const RepDesc *reps;      // device array of replica descriptors
+    const uint32_t *tile_rep; // device: replica of every global tile (unused if nrep == 1)
+    int32_t nrep;
+    int32_t label_bits;       // 32 or 64
+    int32_t max_th;           // largest tile height among the replicas (LDS sizing)
+    int64_t gtile0, gtile_end;
+};
+
+// Per-launch arguments of the flip kernel's finalisation (observables, PCC).
+struct FlipArgs {
+    xy_obs *trace;        // device: trace[trace_row * nrep + replica], or null
+    int64_t trace_row;
+    int32_t nrep;
+    int32_t pad;
+    int64_t window;       // PCC window (0: no PCC accumulation)
+    double dbeta0, dbeta_min;
+    int64_t halve_every;
+    double target;
+    xy_obs *wmean;        // device: window means wmean[wrow * nrep + replica], or null
+    int64_t wrow;
+};
+
+hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s);
+hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s);
+hipError_t launch_bonds(const Launch &lc, bool from_planes, hipStream_t s);
+hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s);
+hipError_t launch_flip(const Launch &lc, const FlipArgs &fa, hipStream_t s);
+hipError_t launch_measure(const Launch &lc, xy_obs *d_out, hipStream_t s);
+hipError_t launch_flatten(const void *d_lab, int32_t label_bits, int64_t N, void *d_out, int32_t out_bits,
+                          hipStream_t s);
+size_t lds_bytes_bonds(int TH);
+size_t lds_bytes_flip(int TH, int label_bits);
+
+}  // namespace xy
