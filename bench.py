@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput of Swendsen-Wang sweeps of the 2D XY model on one MI355X.
+
+Metric: spin updates per second = sweeps x L^2 / wall time.  The headline
+workload is a single L = 4096 lattice at beta = 1.12 from a uniform-angle hot
+start: `--warmup` thermalisation sweeps (default 200) are run untimed, then
+exactly `--steps` sweeps (default 1000) are timed between two device
+synchronisations.  A "step" is one full sweep: mirror direction, link
+activation, labelling, cluster reflection and the observable reductions.
+
+A second, instrumented pass of the same length records HIP events on the
+handle's stream around every kernel launch and every sweep; it gives the
+per-kernel average durations (roofline of the dominant kernel) and the
+per-sweep p50 / p99 latency.  The CPU oracle is timed on a bounded sample of
+the same workload on this host (cpu_baseline).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+KERNELS_SRC = os.path.join(ROOT, "paper_1210_6116_amd", "csrc", "xy_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "counters_L4096.json")
+
+
+def alg_bytes_per_site(kernel: str, label_bytes: int) -> float:
+    """Algorithmic HBM bytes per site of one launch of each kernel.
+
+    bonds_ccl: read both spin planes (8) + write the label (4 or 8) + the two
+               link bit planes (0.25) and the coin bits (0.125)
+    flip:      read the label (4 or 8) and both spin planes (8) + write the
+               spins of flipped clusters (8 x 1/2 in expectation)
+    merge:     only the links that leave a tile (2 per 64 sites): negligible
+    """
+    if kernel == "bonds_ccl":
+        return 8.0 + label_bytes + 0.375
+    if kernel == "flip":
+        return label_bytes + 8.0 + 4.0
+    return 0.0
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def kernel_source_sha() -> str:
+    return hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+
+
+def traffic_from_counters(kernel: str, launches_sites: int):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs,
+    or None when they are missing or were taken on a different kernel source."""
+    try:
+        rec = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return (k["fetch_kib"] + k["write_kib"]) * 1024.0 * rec.get("copy_scale", 1.0)
+
+
+def cpu_baseline(L: int, beta: float, seed: int, nsweeps: int):
+    import oracle
+
+    lat = oracle.Lattice(L=L, beta=beta, seed=seed, storage32=True)
+    t0 = time.perf_counter()
+    lat.run(nsweeps)
+    dt = time.perf_counter() - t0
+    return {"value": nsweeps * L * L / dt, "unit": "spin updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d sweeps of the L=%d, beta=%g lattice from the oracle's own hot start, "
+                      "1 thread (FP64, BFS labelling), %.1f s" % (nsweeps, L, beta, dt),
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--L", type=int, default=4096)
+    ap.add_argument("--beta", type=float, default=1.12)
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--cpu-sweeps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
+    ap.add_argument("--no-instrument", action="store_true", help="skip the instrumented pass")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="first run a plain elementwise copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the sweep on a single MI355X "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1210_6116_amd as xy
+    import xyworkloads as wl
+
+    if args.copy_calib_mb:
+        src = torch.ones(args.copy_calib_mb * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    L, beta = args.L, args.beta
+    N = L * L
+    seed = wl.SEED_L4096
+    print("bench: L=%d beta=%g warmup=%d steps=%d" % (L, beta, args.warmup, args.steps), file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    lat = xy.Lattices(dict(L=L, beta=beta, seed=seed, tile_rows=args.tile_rows), stream=stream)
+    label_bytes = 8 if N >= 2 ** 32 else 4
+
+    lat.sweep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps * N / dt
+    print("bench: timed %d sweeps in %.3f s" % (args.steps, dt), file=sys.stderr, flush=True)
+
+    roofline = None
+    latency = {}
+    kernels = {}
+    if not args.no_instrument:
+        lat.timing(True)
+        evs = []
+        for _ in range(args.steps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lat.sweep(1)
+            b.record(stream)
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        ms, launches = lat.timing_read()
+        lat.timing(False)
+        per_sweep = [a.elapsed_time(b) for a, b in evs]
+        latency = {"sweep_ms_p50": percentile(per_sweep, 50), "sweep_ms_p99": percentile(per_sweep, 99),
+                   "sweep_ms_mean": sum(per_sweep) / len(per_sweep)}
+        for k, name in enumerate(xy._lib.KERNEL_NAMES):
+            if launches[k]:
+                avg = ms[k] / launches[k]
+                ab = alg_bytes_per_site(name, label_bytes) * N
+                kernels[name] = {"launches": int(launches[k]), "avg_ms": avg, "alg_bytes": ab,
+                                 "alg_GBps": (ab / (avg * 1e-3) / 1e9) if ab else None}
+        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+        if kernels[dom]["alg_bytes"] == 0:
+            dom = max((k for k in kernels if kernels[k]["alg_bytes"]),
+                      key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+        kd = kernels[dom]
+        achieved = kd["alg_GBps"]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(dom, N),
+                    "alg_bytes_per_launch": kd["alg_bytes"], "avg_launch_ms": kd["avg_ms"]}
+    lat.close()
+
+    line = {
+        "metric": "spin updates/sec (SW sweeps x L^2 / s)",
+        "value": value,
+        "unit": "spin updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state, f64 reflection and sums",
+        "data": "synthetic (seeded Philox hot start)",
+        "config": {"workload": "plain SW sweep, 2D XY periodic L=%d, beta=%g, uint%d labels, "
+                               "%d thermalisation + %d timed sweeps" % (L, beta, 8 * label_bytes,
+                                                                         args.warmup, args.steps),
+                   "L": L, "beta": beta, "seed": seed, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "latency": latency,
+        "kernels": kernels,
+    }
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

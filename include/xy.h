@@ -145,14 +145,14 @@ int xy_get_sweep(xy_handle *h, int32_t rep, uint64_t *sweep, double r[2]);
 /* Standalone labelling of a given link set (the same kernels as the sweep):
  * d_bx, d_by are device bit planes as in xy_get_bonds; d_labels receives N
  * canonical labels (uint32 if label_bits == 32, uint64 if 64) in device memory.
- * Enqueued on hip_stream (NULL = the default stream); asynchronous. */
+ * Runs on hip_stream (NULL = the default stream) and synchronizes it. */
 int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint32_t *d_bx,
                    const uint32_t *d_by, void *d_labels, void *hip_stream);
 
 /* Per-kernel timing with HIP events on the handle's stream: enable (1) or
  * disable (0) recording; read the accumulated milliseconds and launch counts
  * of each kernel class (XY_K_* below) and reset them (synchronizes). */
-enum { XY_K_BONDS = 0, XY_K_MERGE = 1, XY_K_FLIP = 2, XY_K_FUSED = 3, XY_K_COUNT = 4 };
+enum { XY_K_BONDS = 0, XY_K_MERGE = 1, XY_K_FLIP = 2, XY_K_FUSED = 3, XY_K_FINALIZE = 4, XY_K_COUNT = 5 };
 int xy_timing(xy_handle *h, int32_t enable);
 int xy_timing_read(xy_handle *h, double *ms, int64_t *launches);
 

@@ -126,11 +126,14 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         l.s = off;
         off = align_up(off + (size_t)r.N * 4);
         for (int q = 0; q < 2; ++q) {
+            // edge copies are always double-buffered (the flip reads one slot
+            // and writes the other); labels and link planes only with pingpong
+            l.edge[q] = off;
+            off = align_up(off + (size_t)r.ntiles * (r.TH + r.TW) * sizeof(float2));
             if (q == 1 && !P.pingpong) {
                 l.lab[1] = l.lab[0];
                 l.bx[1] = l.bx[0];
                 l.by[1] = l.by[0];
-                l.edge[1] = l.edge[0];
                 continue;
             }
             l.lab[q] = off;
@@ -139,8 +142,6 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
             off = align_up(off + words * 4);
             l.by[q] = off;
             off = align_up(off + words * 4);
-            l.edge[q] = off;
-            off = align_up(off + (size_t)r.ntiles * (r.TH + r.TW) * sizeof(float2));
         }
         l.coins = off;
         off = align_up(off + std::max<size_t>(words, 4) * 4);
@@ -181,8 +182,8 @@ struct xy_handle {
         hipEvent_t a, b;
     };
     std::vector<Ev> ev_used, ev_free;
-    double ms[XY_K_COUNT] = {0, 0, 0, 0};
-    int64_t launches[XY_K_COUNT] = {0, 0, 0, 0};
+    double ms[XY_K_COUNT] = {};
+    int64_t launches[XY_K_COUNT] = {};
 };
 
 namespace {
@@ -251,6 +252,7 @@ int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa)
     HIPCHECK(h, timed(h, XY_K_BONDS, [&] { return xy::launch_bonds(lc, false, h->stream); }));
     HIPCHECK(h, timed(h, XY_K_MERGE, [&] { return xy::launch_merge(lc, true, h->stream); }));
     HIPCHECK(h, timed(h, XY_K_FLIP, [&] { return xy::launch_flip(lc, fa, h->stream); }));
+    HIPCHECK(h, timed(h, XY_K_FINALIZE, [&] { return xy::launch_finalize(h->d_reps, h->plan.n, fa, nullptr, h->stream); }));
     return XY_OK;
 }
 
@@ -389,8 +391,10 @@ int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_
     if (n > 1)
         HIPCHECK(h, hipMemcpy(h->d_tile_rep, tile_rep.data(), tile_rep.size() * sizeof(uint32_t),
                               hipMemcpyHostToDevice));
-    for (int32_t k = 0; k < n; ++k)
+    for (int32_t k = 0; k < n; ++k) {
         HIPCHECK(h, xy::launch_init_spins(h->d_reps, k, P.res[k].N, p[k].start, h->stream));
+        HIPCHECK(h, xy::launch_edge_refresh(h->d_reps, k, P.res[k].ntiles, h->stream));
+    }
     HIPCHECK(h, xy::launch_init_dir(h->d_reps, n, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     *out = h;
@@ -445,7 +449,8 @@ int xy_measure(xy_handle *h, xy_obs *out)
     if (rc) return rc;
     if (!out) return fail(XY_EINVAL, "out pointer is NULL");
     const xy::Launch lc = launch_all(h);
-    HIPCHECK(h, xy::launch_measure(lc, h->d_meas, h->stream));
+    HIPCHECK(h, xy::launch_measure(lc, h->stream));
+    HIPCHECK(h, xy::launch_finalize(h->d_reps, h->plan.n, no_pcc(h), h->d_meas, h->stream));
     HIPCHECK(h, hipMemcpyAsync(out, h->d_meas, h->plan.n * sizeof(xy_obs), hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     return XY_OK;
@@ -514,6 +519,8 @@ int xy_set_state(xy_handle *h, int32_t rep, const float *cos_in, const float *si
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     HIPCHECK(h, hipMemcpy(d.c, cos_in, d.N * sizeof(float), hipMemcpyHostToDevice));
     HIPCHECK(h, hipMemcpy(d.s, sin_in, d.N * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHECK(h, xy::launch_edge_refresh(h->d_reps, rep, d.ntiles, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
     return XY_OK;
 }
 

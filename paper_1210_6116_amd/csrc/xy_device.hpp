@@ -64,8 +64,7 @@ struct RepState {
     uint64_t t;              // sweeps completed
     double dir[2][2];        // mirror direction of sweep t in slot t&1
     unsigned long long ties[2];  // near ties of sweep t in slot t&1
-    unsigned int done;       // tiles finished in the running reduction
-    unsigned int pad0;
+    uint64_t pad0;
     double acc[8];           // PCC window sums: E, m2, ex, sx, ey, sy, ups_x, N sx^2
     int64_t acc_n;           // sweeps in the running window
     int64_t pcc_k;           // PCC steps taken (halving schedule)

@@ -143,28 +143,34 @@ __device__ void union_lds(uint32_t *lab, uint32_t a, uint32_t b)
 }
 
 // ------------------------------------------------- union-find in global memory
+// Root of v with intermediate pointer jumping: every node on the path is
+// re-pointed at its grandparent.  Parents only ever decrease and stay inside
+// the node's set, so these plain stores are benign even while other threads
+// hook roots: a stale value only shortens less.
 template <typename LT>
-__device__ __forceinline__ LT gload(const LT *p)
+__device__ LT find_jump(LT *lab, LT v)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename LT>
-__device__ LT find_global(const LT *lab, LT x)
-{
+    LT par = lab[v];
+    if (par == v) return v;
+    LT prev = v;
     while (true) {
-        const LT p = gload(&lab[x]);
-        if (p == x) return x;
-        x = p;
+        const LT next = lab[par];
+        if (next == par) return par;
+        lab[prev] = next;
+        prev = par;
+        par = next;
     }
 }
 
+// Lock-free union: the larger root is hooked under the smaller one with an
+// atomic minimum, so every root is the smallest site of its tree.  If the hook
+// target stopped being a root meanwhile, continue with the parent it got.
 template <typename LT>
 __device__ void union_global(LT *lab, LT a, LT b)
 {
     while (true) {
-        a = find_global(lab, a);
-        b = find_global(lab, b);
+        a = find_jump(lab, a);
+        b = find_jump(lab, b);
         if (a == b) return;
         if (a > b) {
             const LT tmp = a;
@@ -175,26 +181,6 @@ __device__ void union_global(LT *lab, LT a, LT b)
         if (old == b) return;
         b = old;
     }
-}
-
-// Root of x in a finished forest (no concurrent hooks); the path is then
-// pointed straight at the root.
-template <typename LT>
-__device__ LT find_compress(LT *lab, LT x)
-{
-    LT r = x;
-    while (true) {
-        const LT p = lab[r];
-        if (p == r) break;
-        r = p;
-    }
-    while (x != r) {
-        const LT p = lab[x];
-        if (p == r) break;
-        lab[x] = r;
-        x = p;
-    }
-    return r;
 }
 
 // --------------------------------------------------------------- init
@@ -208,6 +194,20 @@ __global__ __launch_bounds__(kThreads) void k_init_spins(const RepDesc *__restri
     if (start == XY_START_HOT) disk_point(R.seed, R.rep, TAG_INIT, (uint32_t)i, 0u, false, &x, &y);
     R.c[i] = (float)x;
     R.s[i] = (float)y;
+}
+
+// Edge copies (first column, then first row of every tile) of the current
+// spins, for the sweep that comes next; needed whenever the host sets spins.
+__global__ __launch_bounds__(128) void k_edge_refresh(const RepDesc *__restrict__ reps, int32_t r)
+{
+    const RepDesc &R = reps[r];
+    const int64_t lt = blockIdx.x;
+    const Tile T = make_tile(R, lt);
+    float2 *e = R.edge[R.st->t & 1] + lt * (T.TH + T.TW);
+    for (int k = threadIdx.x; k < T.TH + T.TW; k += blockDim.x) {
+        const int64_t i = k < T.TH ? T.site(k, 0) : T.site(0, k - T.TH);
+        e[k] = make_float2(R.c[i], R.s[i]);
+    }
 }
 
 __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
@@ -246,7 +246,8 @@ __global__ __launch_bounds__(kThreads) void k_bonds_ccl(const RepDesc *__restric
         const float rxf = (float)rx, ryf = (float)ry;
         const float *__restrict__ cp = R.c;
         const float *__restrict__ sp = R.s;
-        // projections a = s . r of the tile, its right halo column and bottom halo row
+        // projections a = s . r of the tile, its right halo column and bottom
+        // halo row (the neighbours' first column / row, from their edge copies)
         for (int k = 0; k < B; ++k) {
             const int y = yb + k;
             if (y < TH && lane < TW) {
@@ -254,19 +255,14 @@ __global__ __launch_bounds__(kThreads) void k_bonds_ccl(const RepDesc *__restric
                 a_s[y * AS + lane] = cp[i] * rxf + sp[i] * ryf;
             }
         }
-        float2 *edge = R.edge[par] + lt * (TH + TW);
         if (wave == 0 && lane < TW) {
-            const int64_t i = (((T.y0 + TH) & Lm) << T.log2L) + T.x0 + lane;
-            a_s[TH * AS + lane] = cp[i] * rxf + sp[i] * ryf;
+            const int64_t ltd = (int64_t)((T.ty + 1) % T.nty) * T.ntx + T.tx;
+            const float2 e = R.edge[par][ltd * (TH + TW) + TH + lane];
+            a_s[TH * AS + lane] = e.x * rxf + e.y * ryf;
         } else if (wave == 1 && lane < TH) {
-            const int64_t i = ((T.y0 + lane) << T.log2L) + ((T.x0 + TW) & Lm);
-            a_s[lane * AS + TW] = cp[i] * rxf + sp[i] * ryf;
-        } else if (wave == 2 && lane < TH) {
-            const int64_t i = T.site(lane, 0);  // first column, seen as halo by the left tile
-            edge[lane] = make_float2(cp[i], sp[i]);
-        } else if (wave == 3 && lane < TW) {
-            const int64_t i = T.site(0, lane);  // first row, seen as halo by the upper tile
-            edge[TH + lane] = make_float2(cp[i], sp[i]);
+            const int64_t ltr = (int64_t)T.ty * T.ntx + (T.tx + 1) % T.ntx;
+            const float2 e = R.edge[par][ltr * (TH + TW) + lane];
+            a_s[lane * AS + TW] = e.x * rxf + e.y * ryf;
         }
         __syncthreads();
 
@@ -491,37 +487,16 @@ __device__ __forceinline__ void obs_from_sums(const double *S, double N, double 
     o->ups_x = o->ex - beta * N * o->sx * o->sx;
 }
 
-// Last tile of a replica to finish: reduce the per-tile partial sums in a
-// fixed order.  Returns true in every thread of that block; the totals are in
-// tot[] of thread 0.
-__device__ bool last_tile_reduce(const RepDesc &R, int64_t lt, double (&v)[kNumSums], double *red,
-                                 double (&tot)[kNumSums])
+// Per-tile partial sums (thread 0 holds the block totals after block_sum).
+// They are combined by k_finalize in a fixed order, one launch later, so no
+// device-wide fence is needed here.
+__device__ __forceinline__ void store_partials(const RepDesc &R, int64_t lt, const double (&v)[kNumSums])
 {
-    __shared__ int is_last;
     if (threadIdx.x == 0) {
         double *dst = R.partials + lt * kNumSums;
 #pragma unroll
         for (int k = 0; k < kNumSums; ++k) dst[k] = v[k];
-        __threadfence();
-        const unsigned prev = atomicAdd(&R.st->done, 1u);
-        is_last = (prev == (unsigned)(R.ntiles - 1));
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double s[kNumSums];
-#pragma unroll
-    for (int k = 0; k < kNumSums; ++k) s[k] = 0.0;
-    for (int64_t j = threadIdx.x; j < R.ntiles; j += kThreads) {
-        const double *src = R.partials + j * kNumSums;
-#pragma unroll
-        for (int k = 0; k < kNumSums; ++k) s[k] += __builtin_nontemporal_load(const_cast<double *>(&src[k]));
-    }
-    __syncthreads();
-    block_sum<kNumSums>(s, red);
-#pragma unroll
-    for (int k = 0; k < kNumSums; ++k) tot[k] = s[k];
-    return true;
 }
 
 // ------------------------------------------------- K3: flip + reductions
@@ -582,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ r
             if (p == (LT)i)
                 m = p;
             else if (!T.contains((uint64_t)p))
-                m = find_compress(lab, p);
+                m = find_jump(lab, p);
             memo[y * TW + lane] = m;
         }
     }
@@ -590,7 +565,7 @@ __global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ r
     // spins from their edge copies), flipped here as their owners flip them
     if (wave == 0 && lane < TH) {
         const int64_t h = ((T.y0 + lane) << T.log2L) + ((T.x0 + TW) & Lm);
-        const LT root = find_compress(lab, (LT)h);
+        const LT root = find_jump(lab, (LT)h);
         const int64_t ltr = (int64_t)T.ty * T.ntx + (T.tx + 1) % T.ntx;
         const float2 e = R.edge[par][ltr * (TH + TW) + lane];
         float c1, s1;
@@ -598,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ r
         spin[lane * SS + TW] = make_float2(c1, s1);
     } else if (wave == 1 && lane < TW) {
         const int64_t h = (((T.y0 + TH) & Lm) << T.log2L) + T.x0 + lane;
-        const LT root = find_compress(lab, (LT)h);
+        const LT root = find_jump(lab, (LT)h);
         const int64_t ltd = (int64_t)((T.ty + 1) % T.nty) * T.ntx + T.tx;
         const float2 e = R.edge[par][ltd * (TH + TW) + TH + lane];
         float c1, s1;
@@ -617,7 +592,7 @@ __global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ r
                 LT x = lab[i];
                 while (true) {
                     if (!T.contains((uint64_t)x)) {
-                        root = find_compress(lab, x);
+                        root = find_jump(lab, x);
                         break;
                     }
                     const LT m = memo[T.local((uint64_t)x)];
@@ -639,6 +614,15 @@ __global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ r
     }
     __syncthreads();
 
+    // edge copies (first column, first row) of the flipped tile for the next sweep
+    {
+        float2 *en = R.edge[par ^ 1] + lt * (TH + TW);
+        if (wave == 2 && lane < TH)
+            en[lane] = spin[lane * SS];
+        else if (wave == 3 && lane < TW)
+            en[TH + lane] = spin[lane];
+    }
+
     // Phase C: link and site sums of the flipped configuration
     double v[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < B; ++k) {
@@ -657,17 +641,44 @@ __global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ r
         }
     }
     block_sum<kNumSums>(v, red);
+    store_partials(R, lt, v);
+}
+
+// ------------------------------------------------- finalise a sweep
+// One block per replica: the per-tile sums in a fixed order, the observables,
+// the PCC window / beta step, and the sweep counter.  measure_out != null:
+// observables of the current configuration only (no counters touched).
+__global__ __launch_bounds__(kThreads) void k_finalize(const RepDesc *__restrict__ reps, FlipArgs fa,
+                                                        xy_obs *measure_out)
+{
+    __shared__ double red[kWaves * kNumSums];
+    const RepDesc &R = reps[blockIdx.x];
+    RepState *st = R.st;
     double tot[kNumSums];
-    if (!last_tile_reduce(R, lt, v, red, tot)) return;
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) tot[k] = 0.0;
+    for (int64_t j = threadIdx.x; j < R.ntiles; j += kThreads) {
+        const double *src = R.partials + j * kNumSums;
+#pragma unroll
+        for (int k = 0; k < kNumSums; ++k) tot[k] += src[k];
+    }
+    block_sum<kNumSums>(tot, red);
     if (threadIdx.x != 0) return;
 
-    // Finalise the sweep: observables, PCC window, counters.
+    const uint64_t t = st->t;
     const double beta = st->beta;
     const double N = (double)R.N;
     xy_obs o;
-    o.sweep = t + 1;
-    o.beta = beta;
     obs_from_sums(tot, N, beta, &o);
+    o.beta = beta;
+    if (measure_out) {
+        o.sweep = t;
+        o.near_ties = 0;
+        measure_out[R.idx] = o;
+        return;
+    }
+    const int par = (int)(t & 1);
+    o.sweep = t + 1;
     o.near_ties = st->ties[par];
     st->ties_total += o.near_ties;
     st->ties[par] = 0ull;
@@ -715,7 +726,6 @@ __global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ r
             st->acc_n = 0;
         }
     }
-    st->done = 0u;
     st->t = t + 1;
 }
 
@@ -723,7 +733,7 @@ __global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ r
 template <typename LT>
 __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict__ reps,
                                                        const uint32_t *__restrict__ tile_rep,
-                                                       int32_t nrep, int64_t gtile0, xy_obs *out)
+                                                       int32_t nrep, int64_t gtile0)
 {
     __shared__ double red[kWaves * kNumSums];
     int64_t lt;
@@ -750,17 +760,7 @@ __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict_
         }
     }
     block_sum<kNumSums>(v, red);
-    double tot[kNumSums];
-    if (!last_tile_reduce(R, lt, v, red, tot)) return;
-    if (threadIdx.x != 0) return;
-    RepState *st = R.st;
-    xy_obs o;
-    o.sweep = st->t;
-    o.beta = st->beta;
-    obs_from_sums(tot, (double)R.N, st->beta, &o);
-    o.near_ties = 0;
-    out[R.idx] = o;
-    st->done = 0u;
+    store_partials(R, lt, v);
 }
 
 // ------------------------------------------------- canonical labels
@@ -795,6 +795,12 @@ hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_
 {
     const int64_t blocks = (N + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_init_spins, dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, start);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_refresh(const RepDesc *d_reps, int32_t r, int64_t ntiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_edge_refresh, dim3((unsigned)ntiles), dim3(128), 0, s, d_reps, r);
     return hipGetLastError();
 }
 
@@ -843,13 +849,19 @@ hipError_t launch_flip(const Launch &lc, const FlipArgs &fa, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_measure(const Launch &lc, xy_obs *d_out, hipStream_t s)
+hipError_t launch_measure(const Launch &lc, hipStream_t s)
 {
     const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
     if (lc.label_bits == 64)
-        hipLaunchKernelGGL((k_measure<unsigned long long>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, d_out);
+        hipLaunchKernelGGL((k_measure<unsigned long long>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
     else
-        hipLaunchKernelGGL((k_measure<uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, d_out);
+        hipLaunchKernelGGL((k_measure<uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)nrep), dim3(kThreads), 0, s, d_reps, fa, measure_out);
     return hipGetLastError();
 }
 

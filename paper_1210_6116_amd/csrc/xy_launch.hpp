@@ -35,11 +35,14 @@ struct FlipArgs {
 };
 
 hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s);
+hipError_t launch_edge_refresh(const RepDesc *d_reps, int32_t r, int64_t ntiles, hipStream_t s);
 hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s);
 hipError_t launch_bonds(const Launch &lc, bool from_planes, hipStream_t s);
 hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s);
 hipError_t launch_flip(const Launch &lc, const FlipArgs &fa, hipStream_t s);
-hipError_t launch_measure(const Launch &lc, xy_obs *d_out, hipStream_t s);
+hipError_t launch_measure(const Launch &lc, hipStream_t s);
+hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out,
+                           hipStream_t s);
 hipError_t launch_flatten(const void *d_lab, int32_t label_bits, int64_t N, void *d_out, int32_t out_bits,
                           hipStream_t s);
 size_t lds_bytes_bonds(int TH);
