@@ -37,14 +37,18 @@ def alg_bytes_per_site(kernel: str, label_bytes: int) -> float:
 
     bonds_ccl: read both spin planes (8) + write the label (4 or 8) + the two
                link bit planes (0.25) and the coin bits (0.125)
-    flip:      read the label (4 or 8) and both spin planes (8) + write the
-               spins of flipped clusters (8 x 1/2 in expectation)
-    merge:     only the links that leave a tile (2 per 64 sites): negligible
+    flip:      read the label (4 or 8), read and write both spin planes (16)
+    fused:     flip of sweep t plus links / labels of sweep t+1 from the same
+               spins: read label, read + write spins, write label, bits
+               (the 24 B/site pass with 32-bit labels)
+    merge, finalize: only tile-edge links / per-tile sums: not counted
     """
     if kernel == "bonds_ccl":
         return 8.0 + label_bytes + 0.375
     if kernel == "flip":
-        return label_bytes + 8.0 + 4.0
+        return label_bytes + 16.0
+    if kernel == "fused":
+        return 2.0 * label_bytes + 16.0 + 0.375
     return 0.0
 
 
@@ -143,23 +147,17 @@ def main():
     latency = {}
     kernels = {}
     if not args.no_instrument:
+        # same call shape as the timed pass (one call of --steps sweeps), with
+        # HIP events around every kernel and every sweep on the handle's stream
         lat.timing(True)
-        evs = []
-        for _ in range(args.steps):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            lat.sweep(1)
-            b.record(stream)
-            evs.append((a, b))
-        torch.cuda.synchronize()
-        ms, launches = lat.timing_read()
+        lat.sweep(args.steps)
+        ms, launches, per_sweep = lat.timing_read(args.steps)
         lat.timing(False)
-        per_sweep = [a.elapsed_time(b) for a, b in evs]
+        per_sweep = list(per_sweep)
         latency = {"sweep_ms_p50": percentile(per_sweep, 50), "sweep_ms_p99": percentile(per_sweep, 99),
                    "sweep_ms_mean": sum(per_sweep) / len(per_sweep)}
         for k, name in enumerate(xy._lib.KERNEL_NAMES):
-            if launches[k]:
+            if launches[k] and name != "sweep":
                 avg = ms[k] / launches[k]
                 ab = alg_bytes_per_site(name, label_bytes) * N
                 kernels[name] = {"launches": int(launches[k]), "avg_ms": avg, "alg_bytes": ab,

@@ -151,10 +151,22 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
 
 /* Per-kernel timing with HIP events on the handle's stream: enable (1) or
  * disable (0) recording; read the accumulated milliseconds and launch counts
- * of each kernel class (XY_K_* below) and reset them (synchronizes). */
-enum { XY_K_BONDS = 0, XY_K_MERGE = 1, XY_K_FLIP = 2, XY_K_FUSED = 3, XY_K_FINALIZE = 4, XY_K_COUNT = 5 };
+ * of each kernel class (XY_K_*) and reset them (synchronizes).  XY_K_SWEEP
+ * brackets whole sweeps (first kernel of the sweep to its finalize).  With
+ * samples non-NULL, up to cap individual sweep durations (ms, in order) are
+ * also copied out and *nsamples receives how many. */
+enum {
+    XY_K_BONDS = 0,    /* link activation + in-tile labelling */
+    XY_K_MERGE = 1,    /* union across tile edges */
+    XY_K_FLIP = 2,     /* root lookup, reflection, sums */
+    XY_K_FUSED = 3,    /* flip of sweep t + links and tile labels of sweep t+1 */
+    XY_K_FINALIZE = 4, /* observables, PCC step, counters */
+    XY_K_SWEEP = 5,
+    XY_K_COUNT = 6
+};
 int xy_timing(xy_handle *h, int32_t enable);
-int xy_timing_read(xy_handle *h, double *ms, int64_t *launches);
+int xy_timing_read(xy_handle *h, double *ms, int64_t *launches, double *samples, int64_t cap,
+                   int64_t *nsamples);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *xy_last_error(void);

@@ -117,8 +117,9 @@ class Lattices:
     def timing(self, enable: bool):
         _lib.xy_timing(self.h, enable)
 
-    def timing_read(self):
-        return _lib.xy_timing_read(self.h)
+    def timing_read(self, max_samples: int = 0):
+        """(ms per kernel class, launches per class, per-sweep durations in ms)."""
+        return _lib.xy_timing_read(self.h, max_samples)
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxy.so")
 
 XY_OK, XY_EINVAL, XY_ENOMEM, XY_EDEVICE, XY_ESTATE, XY_EBUDGET = 0, -1, -2, -3, -4, -5
 XY_START_HOT, XY_START_COLD = 0, 1
-XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_FINALIZE, XY_K_COUNT = 0, 1, 2, 3, 4, 5
-KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize")
+XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_FINALIZE, XY_K_SWEEP, XY_K_COUNT = 0, 1, 2, 3, 4, 5, 6
+KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize", "sweep")
 
 
 class XYError(RuntimeError):
@@ -72,7 +72,8 @@ _SIGS = {
     "xy_label_links": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "xy_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
-    "xy_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int64, _P(ctypes.c_int64)]),
     "xy_last_error": (ctypes.c_char_p, []),
 }
 EXPORTS = tuple(_SIGS)
@@ -174,11 +175,14 @@ def xy_timing(h, enable: bool):
     _check(load().xy_timing(h, int(enable)))
 
 
-def xy_timing_read(h):
+def xy_timing_read(h, max_samples: int = 0):
+    """(ms[XY_K_COUNT], launches[XY_K_COUNT], per-sweep durations in ms)."""
     ms = np.zeros(XY_K_COUNT)
     n = np.zeros(XY_K_COUNT, dtype=np.int64)
-    _check(load().xy_timing_read(h, _ptr(ms), _ptr(n)))
-    return ms, n
+    samples = np.zeros(max(1, max_samples))
+    ns = ctypes.c_int64(0)
+    _check(load().xy_timing_read(h, _ptr(ms), _ptr(n), _ptr(samples), max_samples, ctypes.byref(ns)))
+    return ms, n, samples[:ns.value]
 
 
 def xy_last_error() -> str:

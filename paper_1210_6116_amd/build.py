@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-result", "-I" + os.path.join(ROOT, "include"),
+    "-Wall", "-Wno-unused-result", "-Wno-pass-failed", "-I" + os.path.join(ROOT, "include"),
 ]
 
 

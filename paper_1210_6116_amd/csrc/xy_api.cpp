@@ -50,12 +50,12 @@ struct Resolved {
 
 // Per-replica byte layout inside the arena.
 struct RepLayout {
-    size_t c, s, lab[2], bx[2], by[2], coins, edge[2], partials, end;
+    size_t c, s, lab[2], bx[2], by[2], coins[2], edge[2], partials, end;
 };
 
 struct Plan {
-    int32_t n = 0, label_bits = 32, max_th = 1;
-    bool pingpong = true;
+    int32_t n = 0, label_bits = 32, max_th = 1, uniform_tw = -1, uniform_th = -1;
+    bool pingpong = true, big_index = false;
     std::vector<Resolved> res;
     std::vector<RepLayout> lay;
     size_t off_reps = 0, off_state = 0, off_tile_rep = 0, off_obs = 0, total = 0;
@@ -101,6 +101,7 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
     if (want32 && (need64 || want64)) return fail(XY_EINVAL, "replicas disagree on the label width");
     P.label_bits = (need64 || want64) ? 64 : 32;
     P.pingpong = maxN < (int64_t(1) << 30);
+    P.big_index = maxN > (int64_t(1) << 30);
     const int lb = P.label_bits / 8;
     size_t off = 0;
     P.res.resize(n);
@@ -118,6 +119,8 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         r.nty = (int32_t)(r.L / r.TH);
         r.ntiles = (int64_t)r.ntx * r.nty;
         P.max_th = std::max(P.max_th, r.TH);
+        P.uniform_tw = (P.uniform_tw < 0 || P.uniform_tw == r.TW) ? r.TW : 0;
+        P.uniform_th = (P.uniform_th < 0 || P.uniform_th == r.TH) ? r.TH : 0;
         P.total_tiles += r.ntiles;
         RepLayout &l = P.lay[k];
         const size_t words = (size_t)std::max<int64_t>(1, (r.N + 31) / 32);
@@ -143,8 +146,10 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
             l.by[q] = off;
             off = align_up(off + words * 4);
         }
-        l.coins = off;
-        off = align_up(off + std::max<size_t>(words, 4) * 4);
+        for (int q = 0; q < 2; ++q) {
+            l.coins[q] = off;
+            off = align_up(off + std::max<size_t>(words, 4) * 4);
+        }
         l.partials = off;
         off = align_up(off + (size_t)r.ntiles * xy::kNumSums * sizeof(double));
         l.end = off;
@@ -181,7 +186,8 @@ struct xy_handle {
         int kind;
         hipEvent_t a, b;
     };
-    std::vector<Ev> ev_used, ev_free;
+    std::vector<Ev> ev_used;
+    std::vector<hipEvent_t> ev_pool;
     double ms[XY_K_COUNT] = {};
     int64_t launches[XY_K_COUNT] = {};
 };
@@ -215,9 +221,22 @@ xy::Launch launch_all(xy_handle *h)
     lc.nrep = h->plan.n;
     lc.label_bits = h->plan.label_bits;
     lc.max_th = h->plan.max_th;
+    lc.big_index = h->plan.big_index;
+    lc.uniform_tw = h->plan.uniform_tw;
+    lc.uniform_th = h->plan.uniform_th;
     lc.gtile0 = 0;
     lc.gtile_end = h->plan.total_tiles;
     return lc;
+}
+
+hipError_t take_event(xy_handle *h, hipEvent_t *e)
+{
+    if (!h->ev_pool.empty()) {
+        *e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
 }
 
 // Runs `launch` bracketed by timing events when timing is on.
@@ -226,15 +245,10 @@ hipError_t timed(xy_handle *h, int kind, F launch)
 {
     if (!h->timing) return launch();
     xy_handle::Ev ev;
-    if (!h->ev_free.empty()) {
-        ev = h->ev_free.back();
-        h->ev_free.pop_back();
-    } else {
-        hipError_t e = hipEventCreate(&ev.a);
-        if (e != hipSuccess) return e;
-        e = hipEventCreate(&ev.b);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e0 = take_event(h, &ev.a);
+    if (e0 != hipSuccess) return e0;
+    e0 = take_event(h, &ev.b);
+    if (e0 != hipSuccess) return e0;
     ev.kind = kind;
     hipError_t e = hipEventRecord(ev.a, h->stream);
     if (e != hipSuccess) return e;
@@ -245,14 +259,37 @@ hipError_t timed(xy_handle *h, int kind, F launch)
     return e;
 }
 
-// Enqueues one sweep of every replica.
-int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa)
+// Enqueues one sweep of every replica.  The links of the sweep were already
+// activated and labelled inside the tiles when *ready is set (by the previous
+// sweep's fused pass).  fuse_next: the flip of this sweep also activates and
+// labels the links of the next one (allowed only when beta cannot change in
+// between, i.e. not at the end of a PCC window, and with double buffers).
+int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, bool *ready)
 {
     const xy::Launch lc = launch_all(h);
-    HIPCHECK(h, timed(h, XY_K_BONDS, [&] { return xy::launch_bonds(lc, false, h->stream); }));
+    hipEvent_t sweep_begin = nullptr;
+    if (h->timing) {
+        HIPCHECK(h, take_event(h, &sweep_begin));
+        HIPCHECK(h, hipEventRecord(sweep_begin, h->stream));
+    }
+    if (!*ready) HIPCHECK(h, timed(h, XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, h->stream); }));
     HIPCHECK(h, timed(h, XY_K_MERGE, [&] { return xy::launch_merge(lc, true, h->stream); }));
-    HIPCHECK(h, timed(h, XY_K_FLIP, [&] { return xy::launch_flip(lc, fa, h->stream); }));
-    HIPCHECK(h, timed(h, XY_K_FINALIZE, [&] { return xy::launch_finalize(h->d_reps, h->plan.n, fa, nullptr, h->stream); }));
+    const bool fuse = fuse_next && h->plan.pingpong;
+    if (fuse)
+        HIPCHECK(h, timed(h, XY_K_FUSED, [&] { return xy::launch_tile(lc, xy::TILE_FUSED, h->stream); }));
+    else
+        HIPCHECK(h, timed(h, XY_K_FLIP, [&] { return xy::launch_tile(lc, xy::TILE_FLIP, h->stream); }));
+    HIPCHECK(h, timed(h, XY_K_FINALIZE,
+                      [&] { return xy::launch_finalize(h->d_reps, h->plan.n, fa, nullptr, h->stream); }));
+    *ready = fuse;
+    if (h->timing) {
+        xy_handle::Ev ev;
+        ev.kind = XY_K_SWEEP;
+        ev.a = sweep_begin;
+        HIPCHECK(h, take_event(h, &ev.b));
+        HIPCHECK(h, hipEventRecord(ev.b, h->stream));
+        h->ev_used.push_back(ev);
+    }
     return XY_OK;
 }
 
@@ -364,7 +401,8 @@ int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_
             d.by[q] = reinterpret_cast<uint32_t *>(A + l.by[q]);
             d.edge[q] = reinterpret_cast<float2 *>(A + l.edge[q]);
         }
-        d.coins = reinterpret_cast<uint32_t *>(A + l.coins);
+        d.coins[0] = reinterpret_cast<uint32_t *>(A + l.coins[0]);
+        d.coins[1] = reinterpret_cast<uint32_t *>(A + l.coins[1]);
         d.partials = reinterpret_cast<double *>(A + l.partials);
         d.st = h->d_state + k;
         d.L = r.L;
@@ -409,10 +447,7 @@ int xy_free(xy_handle *h)
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
-    for (auto &e : h->ev_free) {
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
-    }
+    for (auto &e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->own_arena && h->arena) (void)hipFree(h->arena);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -425,13 +460,14 @@ int xy_sweep(xy_handle *h, int64_t nsweeps, xy_obs *trace)
     if (rc) return rc;
     if (nsweeps < 0) return fail(XY_EINVAL, "nsweeps=%lld is negative", (long long)nsweeps);
     const int32_t n = h->plan.n;
+    bool ready = false;
     for (int64_t k = 0; k < nsweeps; ++k) {
         xy::FlipArgs fa = no_pcc(h);
         if (trace) {
             fa.trace = h->d_trace;
             fa.trace_row = k % kTraceChunk;
         }
-        rc = enqueue_sweep(h, fa);
+        rc = enqueue_sweep(h, fa, k + 1 < nsweeps, &ready);
         if (rc) return rc;
         if (trace && (fa.trace_row == kTraceChunk - 1 || k == nsweeps - 1)) {
             const int64_t first = k - fa.trace_row;
@@ -467,6 +503,7 @@ int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_me
         return fail(XY_EINVAL, "bad PCC schedule (dbeta0=%g dbeta_min=%g halve_every=%lld target=%g)",
                     c->dbeta0, c->dbeta_min, (long long)c->halve_every, c->target);
     const int32_t n = h->plan.n;
+    bool ready = false;
     for (int64_t k = 0; k < nsteps; ++k) {
         for (int64_t w = 0; w < c->window; ++w) {
             xy::FlipArgs fa = no_pcc(h);
@@ -479,7 +516,7 @@ int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_me
                 fa.wmean = h->d_wmean;
                 fa.wrow = k % kTraceChunk;
             }
-            rc = enqueue_sweep(h, fa);
+            rc = enqueue_sweep(h, fa, w + 1 < c->window, &ready);
             if (rc) return rc;
         }
         const int64_t row = k % kTraceChunk;
@@ -642,9 +679,12 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     lc.nrep = 1;
     lc.label_bits = label_bits;
     lc.max_th = r.TH;
+    lc.big_index = P.big_index;
+    lc.uniform_tw = P.uniform_tw;
+    lc.uniform_th = P.uniform_th;
     lc.gtile0 = 0;
     lc.gtile_end = r.ntiles;
-    if (e == hipSuccess) e = xy::launch_bonds(lc, true, s);
+    if (e == hipSuccess) e = xy::launch_tile(lc, xy::TILE_PLANES, s);
     if (e == hipSuccess) e = xy::launch_merge(lc, false, s);
     if (e == hipSuccess) e = xy::launch_flatten(d_labels, label_bits, r.N, d_labels, label_bits, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -661,19 +701,24 @@ int xy_timing(xy_handle *h, int32_t enable)
     return XY_OK;
 }
 
-int xy_timing_read(xy_handle *h, double *ms, int64_t *launches)
+int xy_timing_read(xy_handle *h, double *ms, int64_t *launches, double *samples, int64_t cap,
+                   int64_t *nsamples)
 {
     int rc = check_handle(h);
     if (rc) return rc;
     HIPCHECK(h, hipStreamSynchronize(h->stream));
+    int64_t ns = 0;
     for (auto &e : h->ev_used) {
         float t = 0.f;
         HIPCHECK(h, hipEventElapsedTime(&t, e.a, e.b));
         h->ms[e.kind] += t;
         h->launches[e.kind] += 1;
-        h->ev_free.push_back(e);
+        if (e.kind == XY_K_SWEEP && samples && ns < cap) samples[ns++] = t;
+        h->ev_pool.push_back(e.a);
+        h->ev_pool.push_back(e.b);
     }
     h->ev_used.clear();
+    if (nsamples) *nsamples = ns;
     for (int k = 0; k < XY_K_COUNT; ++k) {
         if (ms) ms[k] = h->ms[k];
         if (launches) launches[k] = h->launches[k];

@@ -76,9 +76,9 @@ struct RepDesc {
     float *c, *s;            // spin planes, N floats each
     void *lab[2];            // label forest of sweep t in slot t&1 (uint32 or uint64, N)
     uint32_t *bx[2], *by[2]; // active-link bit planes of sweep t in slot t&1
-    uint32_t *coins;         // flip coins of sweep t, one bit per site
-    float2 *edge[2];         // per tile: pre-flip spins of its first column (TH) then first row (TW)
-    double *partials;        // per tile: kNumSums partial sums
+    uint32_t *coins[2];      // flip coins of sweep t in slot t&1, one bit per site
+    float2 *edge[2];         // spins before sweep t in slot t&1: per tile, its first column (TH) then first row (TW)
+    double *partials;        // kNumSums planes of per-tile sums: partials[k * ntiles + tile]
     RepState *st;
     int64_t L, N;
     int64_t ntiles, tile_base;  // tiles of this replica, first global tile id
@@ -88,42 +88,46 @@ struct RepDesc {
     int32_t idx;             // position of the replica in its handle
 };
 
-// Tile geometry: TW = min(L, 64) columns (one wave64 lane per column) by
-// TH rows; tile (tx, ty) covers columns tx*TW.. and rows ty*TH..
+// Tile geometry in the site-index type IT (uint32_t when N <= 2^30, so that
+// byte offsets of 4-byte arrays fit 32 bits; uint64_t otherwise).  TW =
+// min(L, 64) columns (one wave64 lane per column) by TH rows; tile (tx, ty)
+// covers columns tx*TW.. and rows ty*TH..
+template <typename IT>
 struct Tile {
-    int64_t L;
+    IT L, x0, y0, base;
     int32_t log2L, TW, TH, log2TW, tx, ty, ntx, nty;
-    int64_t x0, y0;
-    __device__ __forceinline__ int64_t site(int32_t ly, int32_t lx) const
+    __device__ __forceinline__ IT site(int ly, int lx) const { return base + ((IT)ly << log2L) + (IT)lx; }
+    __device__ __forceinline__ bool contains(IT i) const
     {
-        return ((y0 + ly) << log2L) + x0 + lx;
+        const IT y = i >> log2L, x = i & (L - 1);
+        return y >= y0 && y < y0 + (IT)TH && x >= x0 && x < x0 + (IT)TW;
     }
-    __device__ __forceinline__ bool contains(uint64_t i) const
+    __device__ __forceinline__ int local(IT i) const
     {
-        const int64_t y = (int64_t)(i >> log2L), x = (int64_t)(i & (uint64_t)(L - 1));
-        return y >= y0 && y < y0 + TH && x >= x0 && x < x0 + TW;
+        const IT y = i >> log2L, x = i & (L - 1);
+        return (int)(((y - y0) << log2TW) + (x - x0));
     }
-    __device__ __forceinline__ int32_t local(uint64_t i) const
-    {
-        const int64_t y = (int64_t)(i >> log2L), x = (int64_t)(i & (uint64_t)(L - 1));
-        return (int32_t)(((y - y0) << log2TW) + (x - x0));
-    }
+    // tiles to the right and below (periodic)
+    __device__ __forceinline__ int64_t right_tile() const { return (int64_t)ty * ntx + (tx + 1) % ntx; }
+    __device__ __forceinline__ int64_t down_tile() const { return (int64_t)((ty + 1) % nty) * ntx + tx; }
 };
 
-__device__ __forceinline__ Tile make_tile(const RepDesc &R, int64_t lt)
+template <typename IT>
+__device__ __forceinline__ Tile<IT> make_tile(const RepDesc &R, int64_t lt)
 {
-    Tile T;
-    T.L = R.L;
+    Tile<IT> T;
+    T.L = (IT)R.L;
     T.log2L = R.log2L;
     T.TW = R.TW;
     T.TH = R.TH;
     T.log2TW = R.log2TW;
     T.ntx = R.ntx;
     T.nty = R.nty;
-    T.tx = (int32_t)(lt % R.ntx);
-    T.ty = (int32_t)(lt / R.ntx);
-    T.x0 = (int64_t)T.tx * R.TW;
-    T.y0 = (int64_t)T.ty * R.TH;
+    T.tx = (int32_t)(lt & (R.ntx - 1));
+    T.ty = (int32_t)(lt >> (R.log2L - R.log2TW));
+    T.x0 = (IT)T.tx * (IT)R.TW;
+    T.y0 = (IT)T.ty * (IT)R.TH;
+    T.base = (T.y0 << T.log2L) + T.x0;
     return T;
 }
 

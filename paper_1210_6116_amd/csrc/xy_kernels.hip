@@ -4,17 +4,21 @@
 // arXiv:1210.6116: Eq. (Hc); the SW / PCC paragraphs; the helicity-modulus
 // definitions of e and s; the simulation paragraph for the PCC parameters).
 //
-// A sweep is three launches over 64-column tiles (one wave64 lane per column):
-//   k_bonds_ccl : mirror-direction projection, link activation (bit planes),
-//                 in-tile union-find in LDS (row runs from wave ballots, then
-//                 vertical unions), tile-local labels, flip-coin table
-//   k_merge     : union of the labels across every active link that leaves a
-//                 tile (lock-free, the larger root always hooked under the
-//                 smaller one, so every final root is its cluster's minimum site)
-//   k_flip      : root lookup, reflection of flipped clusters in FP64 with one
-//                 rounding to the FP32 state, the six link / site sums of the
-//                 flipped state, and (in the last tile of each replica) the
-//                 observables, the PCC window and the sweep counter
+// The lattice is cut into tiles of 64 columns (one wave64 lane per column) by
+// TH rows; one 256-thread workgroup owns a tile and each of its four waves a
+// band of TH/4 rows.  A sweep t is:
+//   k_tile<BONDS>  mirror-direction projections, link activation (bit planes),
+//                  in-tile union-find in LDS (row runs from wave ballots, then
+//                  vertical unions), tile-local labels, flip-coin table
+//   k_merge        union of the labels across every active link that leaves a
+//                  tile (lock-free; the larger root is always hooked under the
+//                  smaller one, so every final root is its cluster's minimum site)
+//   k_tile<FLIP>   root lookup, reflection of flipped clusters in FP64 with one
+//                  rounding to the FP32 state, the six link / site sums of the
+//                  flipped state
+//   k_finalize     per replica: observables, PCC window and beta step, counter
+// k_tile<FUSED> does FLIP for sweep t and BONDS for sweep t+1 in one pass over
+// the spins (used whenever beta cannot change in between).
 // Built with -ffp-contract=off: the FP64 expressions below are evaluated
 // operation by operation, exactly as written.
 #include <hip/hip_runtime.h>
@@ -27,6 +31,9 @@ namespace xy {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kFinThreads = 1024;
+
+enum : int { M_BONDS = 0, M_FLIP = 1, M_FUSED = 2, M_PLANES = 3 };
 
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ const RepDesc &rep_of(const RepDesc *__restrict__ reps,
@@ -74,13 +81,12 @@ __device__ __forceinline__ void compute_direction(const RepDesc &R, uint64_t t)
     R.st->dir[t & 1][1] = ry;
 }
 
-// Exact (FP64) link decision, identical operation order to the definition:
+// Exact (FP64) link decision, in the operation order of the definition:
 // a = c rx + s ry; x = ((2 beta) a_i) a_j; active iff x > 0 and exp(-x) < 1 - u.
-__device__ __noinline__ bool bond_exact(const float *__restrict__ c, const float *__restrict__ s,
-                                        int64_t i, int64_t j, double rx, double ry, double beta,
-                                        uint32_t w, unsigned long long *ties)
+__device__ __noinline__ bool bond_exact(float fci, float fsi, float fcj, float fsj, double rx, double ry,
+                                        double beta, uint32_t w, unsigned long long *ties)
 {
-    const double ci = c[i], si = s[i], cj = c[j], sj = s[j];
+    const double ci = fci, si = fsi, cj = fcj, sj = fsj;
     const double ai = ci * rx + si * ry;
     const double aj = cj * rx + sj * ry;
     const double xb = ((2.0 * beta) * ai) * aj;
@@ -90,23 +96,21 @@ __device__ __noinline__ bool bond_exact(const float *__restrict__ c, const float
     return e < omu;
 }
 
-// FP32 decision with a guard band: the FP32 value of exp(-x) is within
-// ~1e-6 (1 + beta) of the FP64 one for unit spins, so outside |e - (1-u)| <= G
+// FP32 decision with a guard band: for unit spins the FP32 value of exp(-x)
+// is within ~1e-6 (1 + beta) of the FP64 one, so outside |e - (1-u)| <= G
 // both precisions agree; inside it the FP64 decision is taken.
 struct BondCtx {
-    const float *c, *s;
     double rx, ry, beta;
-    float b2f, guard;
+    float rxf, ryf, b2f, guard;
     unsigned long long *ties;
 };
 
-__device__ __forceinline__ bool bond_decide(const BondCtx &B, float ai, float aj, uint32_t w,
-                                            int64_t i, int64_t j)
+__device__ __forceinline__ bool bond_decide(const BondCtx &B, float ai, float aj, uint32_t w, float2 si, float2 sj)
 {
     const float xb = (B.b2f * ai) * aj;
     const float e = xb > 0.0f ? __expf(-xb) : 1.0f;
     const float omu = 1.0f - (float)w * 2.3283064365386963e-10f;
-    if (fabsf(e - omu) <= B.guard) return bond_exact(B.c, B.s, i, j, B.rx, B.ry, B.beta, w, B.ties);
+    if (fabsf(e - omu) <= B.guard) return bond_exact(si.x, si.y, sj.x, sj.y, B.rx, B.ry, B.beta, w, B.ties);
     return e < omu;
 }
 
@@ -116,12 +120,17 @@ __device__ __forceinline__ uint32_t lds_load(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ uint32_t find_lds(const uint32_t *lab, uint32_t x)
+// Root of x with path halving (x skips to its grandparent at every step);
+// the stores are benign for the same reason as in global memory below.
+__device__ __forceinline__ uint32_t find_lds(uint32_t *lab, uint32_t x)
 {
     while (true) {
         const uint32_t p = lds_load(&lab[x]);
         if (p == x) return x;
-        x = p;
+        const uint32_t g = lds_load(&lab[p]);
+        if (g == p) return p;
+        __hip_atomic_store(&lab[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = g;
     }
 }
 
@@ -183,6 +192,51 @@ __device__ void union_global(LT *lab, LT a, LT b)
     }
 }
 
+// --------------------------------------------- reductions (fixed order)
+template <int K, int NW>
+__device__ __forceinline__ void block_sum(double (&v)[K], double *red /* NW*K */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = red[k];
+            for (int w2 = 1; w2 < NW; ++w2) s += red[w2 * K + k];
+            v[k] = s;
+        }
+    }
+}
+
+__device__ __forceinline__ void store_partials(const RepDesc &R, int64_t lt, const double (&v)[kNumSums])
+{
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kNumSums; ++k) R.partials[k * R.ntiles + lt] = v[k];
+    }
+}
+
+// Observables from the six sums (the definitions' formulas); one thread.
+__device__ __forceinline__ void obs_from_sums(const double *S, double N, double beta, xy_obs *o)
+{
+    o->E = -(S[0] + S[2]) / N;
+    o->m2 = (S[4] * S[4] + S[5] * S[5]) / (N * N);
+    o->ex = S[0] / N;
+    o->sx = S[1] / N;
+    o->ey = S[2] / N;
+    o->sy = S[3] / N;
+    o->ups_x = o->ex - beta * N * o->sx * o->sx;
+}
+
 // --------------------------------------------------------------- init
 __global__ __launch_bounds__(kThreads) void k_init_spins(const RepDesc *__restrict__ reps, int32_t r,
                                                           int32_t start)
@@ -202,10 +256,10 @@ __global__ __launch_bounds__(128) void k_edge_refresh(const RepDesc *__restrict_
 {
     const RepDesc &R = reps[r];
     const int64_t lt = blockIdx.x;
-    const Tile T = make_tile(R, lt);
+    const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
     float2 *e = R.edge[R.st->t & 1] + lt * (T.TH + T.TW);
     for (int k = threadIdx.x; k < T.TH + T.TW; k += blockDim.x) {
-        const int64_t i = k < T.TH ? T.site(k, 0) : T.site(0, k - T.TH);
+        const uint64_t i = k < T.TH ? T.site(k, 0) : T.site(0, k - T.TH);
         e[k] = make_float2(R.c[i], R.s[i]);
     }
 }
@@ -217,98 +271,273 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
     compute_direction(reps[r], reps[r].st->t);
 }
 
-// ------------------------------------------------- K1: bonds + tile labelling
-// LDS: a[(TH+1)*(TW+1)] f32 | lab[TW*TH] u32 | bxm[TH], bym[TH] u64
-template <typename LT, bool FROM_PLANES>
-__global__ __launch_bounds__(kThreads) void k_bonds_ccl(const RepDesc *__restrict__ reps,
-                                                         const uint32_t *__restrict__ tile_rep,
-                                                         int32_t nrep, int64_t gtile0)
+// ----------------------------------------------------------- the tile kernel
+// LDS: spin[(TH+1)*(TW+1)] float2 (tile + right halo column + bottom halo row)
+//      | bxm[64], bym[64] u64 row masks of active links
+//      | memo[TW*TH] (LT; FLIP) aliased by lab[TW*TH] (u32; labelling)
+// BT = rows per wave known at compile time (tiles of 64 x 4*BT; every loop
+// over a wave's rows is unrolled and its independent loads are issued
+// together); BT = 0 is the general path for lattices narrower than 64.
+template <typename LT, typename IT, int MODE, int BT>
+__global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ reps,
+                                                    const uint32_t *__restrict__ tile_rep,
+                                                    int32_t nrep, int64_t gtile0)
 {
+    constexpr bool FLIP = MODE == M_FLIP || MODE == M_FUSED;
+    constexpr bool BONDS = MODE == M_BONDS || MODE == M_FUSED;
+    constexpr bool CCL = MODE != M_FLIP;
+    constexpr bool FIXED = BT > 0;
+    constexpr int BMAX = FIXED ? BT : 16;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kWaves * kNumSums];
+
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
-    const Tile T = make_tile(R, lt);
-    const int TW = T.TW, TH = T.TH, AS = TW + 1;
+    const Tile<IT> T = make_tile<IT>(R, lt);
+    const int TW = FIXED ? 64 : T.TW, TH = FIXED ? 4 * BT : T.TH, SS = TW + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int B = band_rows(TH), yb = wave * B;
-    const int64_t L = T.L, Lm = L - 1;
+    const int B = FIXED ? BT : band_rows(TH), yb = wave * B;
+    const IT Lm = T.L - 1;
     RepState *st = R.st;
     const uint64_t t = st->t;
     const int par = (int)(t & 1);
+    const uint64_t tb = MODE == M_FUSED ? t + 1 : t;  // sweep whose links this launch activates
+    const int pb = (int)(tb & 1);
+    // site (yb + k, lane) belongs to this tile (always, for fixed tiles)
+    auto own = [&](int k) -> bool { return FIXED || (yb + k < TH && lane < TW); };
 
-    uint64_t *bxm = (uint64_t *)smem;
+    float2 *spin = (float2 *)smem;
+    uint64_t *bxm = (uint64_t *)(spin + (TH + 1) * SS);
     uint64_t *bym = bxm + 64;
-    uint32_t *lab_s = (uint32_t *)(bym + 64);
-    float *a_s = (float *)(lab_s + TW * TH);
+    LT *memo = (LT *)(bym + 64);
+    uint32_t *lab_s = (uint32_t *)memo;
+    const int64_t ecount = TH + TW;
+    float *__restrict__ cp = R.c;
+    float *__restrict__ sp = R.s;
 
-    if (!FROM_PLANES) {
-        const double rx = st->dir[par][0], ry = st->dir[par][1], beta = st->beta;
-        const float rxf = (float)rx, ryf = (float)ry;
-        const float *__restrict__ cp = R.c;
-        const float *__restrict__ sp = R.s;
-        // projections a = s . r of the tile, its right halo column and bottom
-        // halo row (the neighbours' first column / row, from their edge copies)
+    if constexpr (FLIP) {
+        LT *lab = (LT *)R.lab[par];
+        const uint32_t *__restrict__ coins = R.coins[par];
+        const double rx = st->dir[par][0], ry = st->dir[par][1];
+        const bool renorm = ((t + 1) % kRenormEvery) == 0;
+        const LT UNK = ~(LT)0;
+        auto flip_one = [&](uint32_t coinword, LT root, float c0, float s0, float &c1, float &s1) -> bool {
+            const bool f = (coinword >> (root & 31)) & 1u;
+            double c = c0, s = s0;
+            if (f) {
+                const double g = 2.0 * (c * rx + s * ry);
+                c = (double)(float)(c - g * rx);
+                s = (double)(float)(s - g * ry);
+            }
+            if (renorm) {
+                const double n = sqrt(c * c + s * s);
+                c = (double)(float)(c / n);
+                s = (double)(float)(s / n);
+            }
+            c1 = (float)c;
+            s1 = (float)s;
+            return f || renorm;
+        };
+        // all independent loads of the wave's rows first: parents and spins
+        LT pl[BMAX];
+        float c0[BMAX], s0[BMAX];
+#pragma unroll
         for (int k = 0; k < B; ++k) {
-            const int y = yb + k;
-            if (y < TH && lane < TW) {
-                const int64_t i = T.site(y, lane);
-                a_s[y * AS + lane] = cp[i] * rxf + sp[i] * ryf;
+            if (own(k)) {
+                const IT i = T.site(yb + k, lane);
+                pl[k] = lab[i];
+                c0[k] = cp[i];
+                s0[k] = sp[i];
             }
         }
-        if (wave == 0 && lane < TW) {
-            const int64_t ltd = (int64_t)((T.ty + 1) % T.nty) * T.ntx + T.tx;
-            const float2 e = R.edge[par][ltd * (TH + TW) + TH + lane];
-            a_s[TH * AS + lane] = e.x * rxf + e.y * ryf;
-        } else if (wave == 1 && lane < TH) {
-            const int64_t ltr = (int64_t)T.ty * T.ntx + (T.tx + 1) % T.ntx;
-            const float2 e = R.edge[par][ltr * (TH + TW) + lane];
-            a_s[lane * AS + TW] = e.x * rxf + e.y * ryf;
+        // Phase A: roots of clusters that leave the tile are resolved now
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (own(k)) {
+                const IT i = T.site(yb + k, lane);
+                const LT p = pl[k];
+                LT m = UNK;
+                if (p == (LT)i)
+                    m = p;
+                else if (!T.contains((IT)p))
+                    m = find_jump(lab, p);
+                memo[(yb + k) * TW + lane] = m;
+            }
+        }
+        // halo: right column and bottom row of the neighbouring tiles (spins
+        // before the sweep from their edge copies), flipped here exactly as
+        // their owners flip them
+        if (wave == 0 && lane < TH) {
+            const IT h = ((T.y0 + (IT)lane) << T.log2L) + ((T.x0 + (IT)TW) & Lm);
+            const float2 e = R.edge[par][T.right_tile() * ecount + lane];
+            const LT root = find_jump(lab, (LT)h);
+            float c1, s1;
+            flip_one(coins[root >> 5], root, e.x, e.y, c1, s1);
+            spin[lane * SS + TW] = make_float2(c1, s1);
+        } else if (wave == 1 && lane < TW) {
+            const IT h = (((T.y0 + (IT)TH) & Lm) << T.log2L) + T.x0 + (IT)lane;
+            const float2 e = R.edge[par][T.down_tile() * ecount + TH + lane];
+            const LT root = find_jump(lab, (LT)h);
+            float c1, s1;
+            flip_one(coins[root >> 5], root, e.x, e.y, c1, s1);
+            spin[TH * SS + lane] = make_float2(c1, s1);
         }
         __syncthreads();
+        // Phase B: roots of the remaining sites via the tile memo, coins, flip
+        LT root[BMAX];
+        uint32_t cw[BMAX];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (own(k)) {
+                LT rt = memo[(yb + k) * TW + lane];
+                if (rt == UNK) {
+                    LT x = pl[k];
+                    while (true) {
+                        if (!T.contains((IT)x)) {
+                            rt = find_jump(lab, x);
+                            break;
+                        }
+                        const LT m = memo[T.local((IT)x)];
+                        if (m != UNK) {
+                            rt = m;
+                            break;
+                        }
+                        x = lab[x];
+                    }
+                }
+                root[k] = rt;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (own(k)) cw[k] = coins[root[k] >> 5];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (own(k)) {
+                const IT i = T.site(yb + k, lane);
+                float c1, s1;
+                if (flip_one(cw[k], root[k], c0[k], s0[k], c1, s1)) {
+                    cp[i] = c1;
+                    sp[i] = s1;
+                }
+                spin[(yb + k) * SS + lane] = make_float2(c1, s1);
+            }
+        }
+        __syncthreads();
+        // edge copies (first column, first row) of the flipped tile for sweep t+1
+        float2 *en = R.edge[par ^ 1] + lt * ecount;
+        if (wave == 2 && lane < TH)
+            en[lane] = spin[lane * SS];
+        else if (wave == 3 && lane < TW)
+            en[TH + lane] = spin[lane];
+    } else if constexpr (MODE == M_BONDS) {
+        // spins before the sweep: own sites from the planes, halo from edge copies
+        float c0[BMAX], s0[BMAX];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (own(k)) {
+                const IT i = T.site(yb + k, lane);
+                c0[k] = cp[i];
+                s0[k] = sp[i];
+            }
+        }
+        if (wave == 0 && lane < TW)
+            spin[TH * SS + lane] = R.edge[par][T.down_tile() * ecount + TH + lane];
+        else if (wave == 1 && lane < TH)
+            spin[lane * SS + TW] = R.edge[par][T.right_tile() * ecount + lane];
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (own(k)) spin[(yb + k) * SS + lane] = make_float2(c0[k], s0[k]);
+        __syncthreads();
+    }
 
+    // ---- link sums of the flipped tile and / or link activation of sweep tb
+    double v[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (FLIP || BONDS) {
         BondCtx ctx;
-        ctx.c = cp;
-        ctx.s = sp;
-        ctx.rx = rx;
-        ctx.ry = ry;
-        ctx.beta = beta;
-        ctx.b2f = (float)(2.0 * beta);
-        ctx.guard = 1e-5f * (1.0f + (float)beta);
-        ctx.ties = &st->ties[par];
-        const uint32_t key0 = (uint32_t)R.seed, key1 = (uint32_t)(R.seed >> 32);
+        uint32_t key0 = 0, key1 = 0;
+        if constexpr (BONDS) {
+            ctx.rx = st->dir[pb][0];
+            ctx.ry = st->dir[pb][1];
+            ctx.beta = st->beta;
+            ctx.rxf = (float)ctx.rx;
+            ctx.ryf = (float)ctx.ry;
+            ctx.b2f = (float)(2.0 * ctx.beta);
+            ctx.guard = 1e-5f * (1.0f + (float)ctx.beta);
+            ctx.ties = &st->ties[pb];
+            key0 = (uint32_t)R.seed;
+            key1 = (uint32_t)(R.seed >> 32);
+        }
         U4 w = {0u, 0u, 0u, 0u};
+#pragma unroll
         for (int k = 0; k < B; ++k) {
             const int y = yb + k;
-            if (y >= TH) break;
-            const int64_t gy = T.y0 + y;
+            if (!FIXED && y >= TH) break;
             bool xa = false, ya = false;
-            if (lane < TW) {
-                const int64_t gx = T.x0 + lane;
-                if (k == 0 || (gy & 1) == 0)
-                    w = philox4x32_10((uint32_t)(((gy >> 1) << T.log2L) + gx), R.rep, (uint32_t)t,
-                                      TAG_BOND, key0, key1);
-                const uint32_t wx = (gy & 1) ? w.z : w.x;
-                const uint32_t wy = (gy & 1) ? w.w : w.y;
-                const int64_t i = (gy << T.log2L) + gx;
-                const float ai = a_s[y * AS + lane];
-                xa = bond_decide(ctx, ai, a_s[y * AS + lane + 1], wx, i,
-                                 (gy << T.log2L) + ((gx + 1) & Lm));
-                ya = bond_decide(ctx, ai, a_s[(y + 1) * AS + lane], wy, i,
-                                 (((gy + 1) & Lm) << T.log2L) + gx);
+            if (FIXED || lane < TW) {
+                const float2 a = spin[y * SS + lane];
+                const float2 r = spin[y * SS + lane + 1];
+                const float2 d = spin[(y + 1) * SS + lane];
+                if constexpr (FLIP) {
+                    const double ci = a.x, si = a.y, cr = r.x, sr = r.y, cd = d.x, sd = d.y;
+                    v[0] += ci * cr + si * sr;
+                    v[1] += si * cr - ci * sr;
+                    v[2] += ci * cd + si * sd;
+                    v[3] += si * cd - ci * sd;
+                    v[4] += ci;
+                    v[5] += si;
+                }
+                if constexpr (BONDS) {
+                    const IT gy = T.y0 + (IT)y;
+                    // one Philox block serves the vertical site pair (2m, 2m+1)
+                    if (FIXED ? (k % 2 == 0) : (k == 0 || (gy & 1) == 0))
+                        w = philox4x32_10((uint32_t)(((gy >> 1) << T.log2L) + T.x0 + (IT)lane), R.rep,
+                                          (uint32_t)tb, TAG_BOND, key0, key1);
+                    const uint32_t wx = (gy & 1) ? w.z : w.x;
+                    const uint32_t wy = (gy & 1) ? w.w : w.y;
+                    const float ai = a.x * ctx.rxf + a.y * ctx.ryf;
+                    const float ar = r.x * ctx.rxf + r.y * ctx.ryf;
+                    const float ad = d.x * ctx.rxf + d.y * ctx.ryf;
+                    xa = bond_decide(ctx, ai, ar, wx, a, r);
+                    ya = bond_decide(ctx, ai, ad, wy, a, d);
+                }
             }
-            const uint64_t mx = __ballot(xa), my = __ballot(ya);
-            if (lane == 0) {
-                bxm[y] = mx;
-                bym[y] = my;
+            if constexpr (BONDS) {
+                const uint64_t mx = __ballot(xa), my = __ballot(ya);
+                if (lane == 0) {
+                    bxm[y] = mx;
+                    bym[y] = my;
+                }
             }
         }
-        __syncthreads();
-        // active-link bit planes of this sweep
-        uint32_t *gbx = R.bx[par], *gby = R.by[par];
+    }
+    if constexpr (FLIP) {
+        block_sum<kNumSums, kWaves>(v, red);
+        store_partials(R, lt, v);
+    }
+    if constexpr (MODE == M_PLANES) {
+        const uint32_t *gbx = R.bx[pb], *gby = R.by[pb];
+        for (int y = threadIdx.x; y < TH; y += kThreads) {
+            uint64_t mx = 0, my = 0;
+            for (int x = 0; x < TW; ++x) {
+                const IT i = T.site(y, x);
+                mx |= (uint64_t)((gbx[i >> 5] >> (i & 31)) & 1u) << x;
+                my |= (uint64_t)((gby[i >> 5] >> (i & 31)) & 1u) << x;
+            }
+            bxm[y] = mx;
+            bym[y] = my;
+        }
+    }
+    if constexpr (!CCL) return;
+
+    __syncthreads();
+    if constexpr (BONDS) {
+        // active-link bit planes of sweep tb
+        uint32_t *gbx = R.bx[pb], *gby = R.by[pb];
         if (TW == 64) {
             for (int j = threadIdx.x; j < 2 * TH; j += kThreads) {
                 const int y = j >> 1, half = j & 1;
-                const int64_t word = (T.site(y, 0) >> 5) + half;
+                const IT word = (T.site(y, 0) >> 5) + (IT)half;
                 gbx[word] = (uint32_t)(bxm[y] >> (32 * half));
                 gby[word] = (uint32_t)(bym[y] >> (32 * half));
             }
@@ -325,51 +554,39 @@ __global__ __launch_bounds__(kThreads) void k_bonds_ccl(const RepDesc *__restric
                     vx |= (uint32_t)((bxm[y] >> x) & 1ull) << b;
                     vy |= (uint32_t)((bym[y] >> x) & 1ull) << b;
                 }
-                const int64_t word = (T.site(0, 0) >> 5) + j;
+                const IT word = (T.base >> 5) + (IT)j;
                 gbx[word] = vx;
                 gby[word] = vy;
             }
         }
-        // flip-coin table of this sweep: this tile's share of the N/128 blocks
-        const int64_t N = R.N;
-        if (N >= 128) {
+        // flip-coin table of sweep tb: this tile's share of the N/128 blocks
+        uint32_t *coins = R.coins[pb];
+        if (R.N >= 128) {
             const int nc = (TW * TH) >> 7;
             for (int j = threadIdx.x; j < nc; j += kThreads) {
                 const int64_t cb = lt * nc + j;
-                const U4 o = philox4x32_10((uint32_t)cb, R.rep, (uint32_t)t, TAG_FLIP, key0, key1);
-                uint4 *dst = (uint4 *)(R.coins + cb * 4);
-                *dst = make_uint4(o.x, o.y, o.z, o.w);
+                const U4 o = philox4x32_10((uint32_t)cb, R.rep, (uint32_t)tb, TAG_FLIP, (uint32_t)R.seed,
+                                           (uint32_t)(R.seed >> 32));
+                *(uint4 *)(coins + cb * 4) = make_uint4(o.x, o.y, o.z, o.w);
             }
         } else if (lt == 0 && threadIdx.x == 0) {
-            const U4 o = philox4x32_10(0u, R.rep, (uint32_t)t, TAG_FLIP, key0, key1);
-            R.coins[0] = o.x;
-            R.coins[1] = o.y;
-            R.coins[2] = o.z;
-            R.coins[3] = o.w;
+            const U4 o = philox4x32_10(0u, R.rep, (uint32_t)tb, TAG_FLIP, (uint32_t)R.seed,
+                                       (uint32_t)(R.seed >> 32));
+            coins[0] = o.x;
+            coins[1] = o.y;
+            coins[2] = o.z;
+            coins[3] = o.w;
         }
-    } else {
-        // given link planes (standalone labelling): gather this tile's row masks
-        const uint32_t *gbx = R.bx[par], *gby = R.by[par];
-        for (int y = threadIdx.x; y < TH; y += kThreads) {
-            uint64_t mx = 0, my = 0;
-            for (int x = 0; x < TW; ++x) {
-                const int64_t i = T.site(y, x);
-                mx |= (uint64_t)((gbx[i >> 5] >> (i & 31)) & 1u) << x;
-                my |= (uint64_t)((gby[i >> 5] >> (i & 31)) & 1u) << x;
-            }
-            bxm[y] = mx;
-            bym[y] = my;
-        }
-        __syncthreads();
     }
 
-    // ---- in-tile labelling
+    // ---- in-tile labelling of sweep tb
     const uint64_t twmask = TW == 64 ? ~0ull : ((1ull << TW) - 1ull);
     const uint64_t inner = twmask >> 1;  // link x -> x+1 stays inside the tile
     // 1) row runs: each site points at the first site of its run of x-links
+#pragma unroll
     for (int k = 0; k < B; ++k) {
-        const int y = yb + k;
-        if (y < TH && lane < TW) {
+        if (own(k)) {
+            const int y = yb + k;
             const uint64_t breaks = ~(bxm[y] & inner) & ((1ull << lane) - 1ull);
             const int start = breaks ? 64 - __clzll((long long)breaks) : 0;
             lab_s[y * TW + lane] = (uint32_t)(y * TW + start);
@@ -378,31 +595,35 @@ __global__ __launch_bounds__(kThreads) void k_bonds_ccl(const RepDesc *__restric
     __syncthreads();
     // 2) vertical links inside the tile; a link whose left neighbour joins the
     //    same two runs is skipped
+#pragma unroll
     for (int k = 0; k < B; ++k) {
         const int y = yb + k;
-        if (y < TH - 1 && lane < TW) {
-            const uint64_t v = bym[y] & twmask;
+        if (own(k) && y < TH - 1) {
+            const uint64_t vv = bym[y] & twmask;
             const uint64_t h0 = bxm[y] & inner, h1 = bxm[y + 1] & inner;
-            const uint64_t need = v & ~(v & (v << 1) & (h0 << 1) & (h1 << 1));
-            if ((need >> lane) & 1ull) union_lds(lab_s, (uint32_t)(y * TW + lane), (uint32_t)((y + 1) * TW + lane));
+            const uint64_t need = vv & ~(vv & (vv << 1) & (h0 << 1) & (h1 << 1));
+            if ((need >> lane) & 1ull)
+                union_lds(lab_s, (uint32_t)(y * TW + lane), (uint32_t)((y + 1) * TW + lane));
         }
     }
     __syncthreads();
     // 3) tile-local roots as global site indices
-    LT *lab = (LT *)R.lab[par];
-    for (int k = 0; k < B; ++k) {
-        const int y = yb + k;
-        if (y < TH && lane < TW) {
-            const uint32_t r = find_lds(lab_s, (uint32_t)(y * TW + lane));
-            lab[T.site(y, lane)] = (LT)T.site((int)(r >> T.log2TW), (int)(r & (TW - 1)));
-        }
-    }
+    LT *labn = (LT *)R.lab[pb];
+    uint32_t lr[BMAX];
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+        if (own(k)) lr[k] = find_lds(lab_s, (uint32_t)((yb + k) * TW + lane));
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+        if (own(k))
+            labn[T.site(yb + k, lane)] = (LT)T.site((int)(lr[k] >> T.log2TW), (int)(lr[k] & (TW - 1)));
 }
 
-// ------------------------------------------------- K2: merge across tiles
+// ------------------------------------------------- merge across tiles
 // One wave per (tile, edge): edge 0 = links leaving the right column, edge 1 =
-// links leaving the bottom row.
-template <typename LT>
+// links leaving the bottom row.  Also computes the mirror direction of the
+// next sweep (tile 0 of each replica).
+template <typename LT, typename IT>
 __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ reps,
                                                      const uint32_t *__restrict__ tile_rep,
                                                      int32_t nrep, int64_t gtile0, int64_t gtile_end,
@@ -415,23 +636,23 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
     if (gtile >= gtile_end) return;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
-    const Tile T = make_tile(R, lt);
-    const int64_t Lm = T.L - 1;
+    const Tile<IT> T = make_tile<IT>(R, lt);
+    const IT Lm = T.L - 1;
     const uint64_t t = R.st->t;
     const int par = (int)(t & 1);
     LT *lab = (LT *)R.lab[par];
     bool on = false;
-    int64_t i = 0, j = 0;
+    IT i = 0, j = 0;
     if (edge == 0) {
         if (lane < T.TH) {
-            const int64_t gy = T.y0 + lane, gx = T.x0 + T.TW - 1;
+            const IT gy = T.y0 + (IT)lane, gx = T.x0 + (IT)T.TW - 1;
             i = (gy << T.log2L) + gx;
             on = (R.bx[par][i >> 5] >> (i & 31)) & 1u;
             j = (gy << T.log2L) + ((gx + 1) & Lm);
         }
     } else {
         if (lane < T.TW) {
-            const int64_t gy = T.y0 + T.TH - 1, gx = T.x0 + lane;
+            const IT gy = T.y0 + (IT)T.TH - 1, gx = T.x0 + (IT)lane;
             i = (gy << T.log2L) + gx;
             on = (R.by[par][i >> 5] >> (i & 31)) & 1u;
             j = (((gy + 1) & Lm) << T.log2L) + gx;
@@ -449,220 +670,25 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
     if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
 }
 
-// --------------------------------------------- reductions (fixed order)
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double *red /* kWaves*K */)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = red[k];
-            for (int w2 = 1; w2 < kWaves; ++w2) s += red[w2 * K + k];
-            v[k] = s;
-        }
-    }
-}
-
-// Observables from the six sums (same formulas as the definitions): called by
-// one thread.
-__device__ __forceinline__ void obs_from_sums(const double *S, double N, double beta, xy_obs *o)
-{
-    o->E = -(S[0] + S[2]) / N;
-    o->m2 = (S[4] * S[4] + S[5] * S[5]) / (N * N);
-    o->ex = S[0] / N;
-    o->sx = S[1] / N;
-    o->ey = S[2] / N;
-    o->sy = S[3] / N;
-    o->ups_x = o->ex - beta * N * o->sx * o->sx;
-}
-
-// Per-tile partial sums (thread 0 holds the block totals after block_sum).
-// They are combined by k_finalize in a fixed order, one launch later, so no
-// device-wide fence is needed here.
-__device__ __forceinline__ void store_partials(const RepDesc &R, int64_t lt, const double (&v)[kNumSums])
-{
-    if (threadIdx.x == 0) {
-        double *dst = R.partials + lt * kNumSums;
-#pragma unroll
-        for (int k = 0; k < kNumSums; ++k) dst[k] = v[k];
-    }
-}
-
-// ------------------------------------------------- K3: flip + reductions
-// LDS: memo[TW*TH] LT | post-flip spins sp[(TH+1)*(TW+1)] float2 | red
-template <typename LT>
-__global__ __launch_bounds__(kThreads) void k_flip(const RepDesc *__restrict__ reps,
-                                                    const uint32_t *__restrict__ tile_rep,
-                                                    int32_t nrep, int64_t gtile0, FlipArgs fa)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kWaves * kNumSums];
-    int64_t lt;
-    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
-    const Tile T = make_tile(R, lt);
-    const int TW = T.TW, TH = T.TH, SS = TW + 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int B = band_rows(TH), yb = wave * B;
-    const int64_t Lm = T.L - 1;
-    RepState *st = R.st;
-    const uint64_t t = st->t;
-    const int par = (int)(t & 1);
-    const double rx = st->dir[par][0], ry = st->dir[par][1];
-    const bool renorm = ((t + 1) % kRenormEvery) == 0;
-    LT *lab = (LT *)R.lab[par];
-    const uint32_t *__restrict__ coins = R.coins;
-    float *__restrict__ cp = R.c;
-    float *__restrict__ sp = R.s;
-    const LT UNK = ~(LT)0;
-
-    LT *memo = (LT *)smem;
-    float2 *spin = (float2 *)(memo + TW * TH);
-
-    auto flip_one = [&](LT root, float c0, float s0, float &c1, float &s1) -> bool {
-        const bool f = (coins[root >> 5] >> (root & 31)) & 1u;
-        double c = c0, s = s0;
-        if (f) {
-            const double g = 2.0 * (c * rx + s * ry);
-            c = (double)(float)(c - g * rx);
-            s = (double)(float)(s - g * ry);
-        }
-        if (renorm) {
-            const double n = sqrt(c * c + s * s);
-            c = (double)(float)(c / n);
-            s = (double)(float)(s / n);
-        }
-        c1 = (float)c;
-        s1 = (float)s;
-        return f || renorm;
-    };
-
-    // Phase A: parents; roots of clusters that leave the tile are resolved now
-    for (int k = 0; k < B; ++k) {
-        const int y = yb + k;
-        if (y < TH && lane < TW) {
-            const int64_t i = T.site(y, lane);
-            const LT p = lab[i];
-            LT m = UNK;
-            if (p == (LT)i)
-                m = p;
-            else if (!T.contains((uint64_t)p))
-                m = find_jump(lab, p);
-            memo[y * TW + lane] = m;
-        }
-    }
-    // halo: right column and bottom row of the neighbouring tiles (pre-flip
-    // spins from their edge copies), flipped here as their owners flip them
-    if (wave == 0 && lane < TH) {
-        const int64_t h = ((T.y0 + lane) << T.log2L) + ((T.x0 + TW) & Lm);
-        const LT root = find_jump(lab, (LT)h);
-        const int64_t ltr = (int64_t)T.ty * T.ntx + (T.tx + 1) % T.ntx;
-        const float2 e = R.edge[par][ltr * (TH + TW) + lane];
-        float c1, s1;
-        flip_one(root, e.x, e.y, c1, s1);
-        spin[lane * SS + TW] = make_float2(c1, s1);
-    } else if (wave == 1 && lane < TW) {
-        const int64_t h = (((T.y0 + TH) & Lm) << T.log2L) + T.x0 + lane;
-        const LT root = find_jump(lab, (LT)h);
-        const int64_t ltd = (int64_t)((T.ty + 1) % T.nty) * T.ntx + T.tx;
-        const float2 e = R.edge[par][ltd * (TH + TW) + TH + lane];
-        float c1, s1;
-        flip_one(root, e.x, e.y, c1, s1);
-        spin[TH * SS + lane] = make_float2(c1, s1);
-    }
-    __syncthreads();
-
-    // Phase B: roots of the remaining sites via the tile memo, then the flip
-    for (int k = 0; k < B; ++k) {
-        const int y = yb + k;
-        if (y < TH && lane < TW) {
-            const int64_t i = T.site(y, lane);
-            LT root = memo[y * TW + lane];
-            if (root == UNK) {
-                LT x = lab[i];
-                while (true) {
-                    if (!T.contains((uint64_t)x)) {
-                        root = find_jump(lab, x);
-                        break;
-                    }
-                    const LT m = memo[T.local((uint64_t)x)];
-                    if (m != UNK) {
-                        root = m;
-                        break;
-                    }
-                    x = lab[x];
-                }
-            }
-            const float c0 = cp[i], s0 = sp[i];
-            float c1, s1;
-            if (flip_one(root, c0, s0, c1, s1)) {
-                cp[i] = c1;
-                sp[i] = s1;
-            }
-            spin[y * SS + lane] = make_float2(c1, s1);
-        }
-    }
-    __syncthreads();
-
-    // edge copies (first column, first row) of the flipped tile for the next sweep
-    {
-        float2 *en = R.edge[par ^ 1] + lt * (TH + TW);
-        if (wave == 2 && lane < TH)
-            en[lane] = spin[lane * SS];
-        else if (wave == 3 && lane < TW)
-            en[TH + lane] = spin[lane];
-    }
-
-    // Phase C: link and site sums of the flipped configuration
-    double v[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < B; ++k) {
-        const int y = yb + k;
-        if (y < TH && lane < TW) {
-            const float2 a = spin[y * SS + lane];
-            const float2 r = spin[y * SS + lane + 1];
-            const float2 d = spin[(y + 1) * SS + lane];
-            const double ci = a.x, si = a.y, cr = r.x, sr = r.y, cd = d.x, sd = d.y;
-            v[0] += ci * cr + si * sr;
-            v[1] += si * cr - ci * sr;
-            v[2] += ci * cd + si * sd;
-            v[3] += si * cd - ci * sd;
-            v[4] += ci;
-            v[5] += si;
-        }
-    }
-    block_sum<kNumSums>(v, red);
-    store_partials(R, lt, v);
-}
-
 // ------------------------------------------------- finalise a sweep
 // One block per replica: the per-tile sums in a fixed order, the observables,
 // the PCC window / beta step, and the sweep counter.  measure_out != null:
 // observables of the current configuration only (no counters touched).
-__global__ __launch_bounds__(kThreads) void k_finalize(const RepDesc *__restrict__ reps, FlipArgs fa,
-                                                        xy_obs *measure_out)
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restrict__ reps, FlipArgs fa,
+                                                           xy_obs *measure_out)
 {
-    __shared__ double red[kWaves * kNumSums];
+    __shared__ double red[(kFinThreads / 64) * kNumSums];
     const RepDesc &R = reps[blockIdx.x];
     RepState *st = R.st;
     double tot[kNumSums];
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) tot[k] = 0.0;
-    for (int64_t j = threadIdx.x; j < R.ntiles; j += kThreads) {
-        const double *src = R.partials + j * kNumSums;
+    const int64_t nt = R.ntiles;
+    for (int64_t j = threadIdx.x; j < nt; j += kFinThreads) {
 #pragma unroll
-        for (int k = 0; k < kNumSums; ++k) tot[k] += src[k];
+        for (int k = 0; k < kNumSums; ++k) tot[k] += R.partials[k * nt + j];
     }
-    block_sum<kNumSums>(tot, red);
+    block_sum<kNumSums, kFinThreads / 64>(tot, red);
     if (threadIdx.x != 0) return;
 
     const uint64_t t = st->t;
@@ -730,7 +756,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const RepDesc *__restrict
 }
 
 // ------------------------------------------------- measure (no update)
-template <typename LT>
+template <typename IT>
 __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict__ reps,
                                                        const uint32_t *__restrict__ tile_rep,
                                                        int32_t nrep, int64_t gtile0)
@@ -738,18 +764,18 @@ __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict_
     __shared__ double red[kWaves * kNumSums];
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
-    const Tile T = make_tile(R, lt);
+    const Tile<IT> T = make_tile<IT>(R, lt);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int B = band_rows(T.TH), yb = wave * B;
-    const int64_t Lm = T.L - 1;
+    const IT Lm = T.L - 1;
     double v[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < B; ++k) {
         const int y = yb + k;
         if (y < T.TH && lane < T.TW) {
-            const int64_t gy = T.y0 + y, gx = T.x0 + lane;
-            const int64_t i = (gy << T.log2L) + gx;
-            const int64_t jr = (gy << T.log2L) + ((gx + 1) & Lm);
-            const int64_t jd = (((gy + 1) & Lm) << T.log2L) + gx;
+            const IT gy = T.y0 + (IT)y, gx = T.x0 + (IT)lane;
+            const IT i = (gy << T.log2L) + gx;
+            const IT jr = (gy << T.log2L) + ((gx + 1) & Lm);
+            const IT jd = (((gy + 1) & Lm) << T.log2L) + gx;
             const double ci = R.c[i], si = R.s[i], cr = R.c[jr], sr = R.s[jr], cd = R.c[jd], sd = R.s[jd];
             v[0] += ci * cr + si * sr;
             v[1] += si * cr - ci * sr;
@@ -759,7 +785,7 @@ __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict_
             v[5] += si;
         }
     }
-    block_sum<kNumSums>(v, red);
+    block_sum<kNumSums, kWaves>(v, red);
     store_partials(R, lt, v);
 }
 
@@ -783,12 +809,10 @@ __global__ __launch_bounds__(kThreads) void k_flatten(const LT *__restrict__ lab
 }
 
 // ====================================================== host-side launchers
-static size_t lds_bonds(int TH) { return 2 * 64 * sizeof(uint64_t) + 64 * TH * sizeof(uint32_t) + (TH + 1) * 65 * sizeof(float); }
-
-template <typename LT>
-static size_t lds_flip(int TH)
+size_t lds_bytes_tile(int TH, int label_bits)
 {
-    return 64 * TH * sizeof(LT) + (TH + 1) * 65 * sizeof(float2);
+    const size_t memo = (size_t)64 * TH * (label_bits == 64 ? 8 : 4);
+    return (size_t)(TH + 1) * 65 * sizeof(float2) + 2 * 64 * sizeof(uint64_t) + memo;
 }
 
 hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s)
@@ -810,20 +834,47 @@ hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_bonds(const Launch &lc, bool from_planes, hipStream_t s)
+template <int MODE, int BT>
+static void tile_dispatch_bt(const Launch &lc, hipStream_t s)
 {
-    const size_t lds = lds_bonds(lc.max_th);
+    const size_t lds = lds_bytes_tile(lc.max_th, lc.label_bits);
     const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
     if (lc.label_bits == 64) {
-        if (from_planes)
-            hipLaunchKernelGGL((k_bonds_ccl<unsigned long long, true>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+        if (lc.big_index)
+            hipLaunchKernelGGL((k_tile<unsigned long long, uint64_t, MODE, BT>), grid, block, lds, s, lc.reps,
+                               lc.tile_rep, lc.nrep, lc.gtile0);
         else
-            hipLaunchKernelGGL((k_bonds_ccl<unsigned long long, false>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+            hipLaunchKernelGGL((k_tile<unsigned long long, uint32_t, MODE, BT>), grid, block, lds, s, lc.reps,
+                               lc.tile_rep, lc.nrep, lc.gtile0);
     } else {
-        if (from_planes)
-            hipLaunchKernelGGL((k_bonds_ccl<uint32_t, true>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
-        else
-            hipLaunchKernelGGL((k_bonds_ccl<uint32_t, false>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+        hipLaunchKernelGGL((k_tile<uint32_t, uint32_t, MODE, BT>), grid, block, lds, s, lc.reps, lc.tile_rep,
+                           lc.nrep, lc.gtile0);
+    }
+}
+
+// Fixed-size tiles (64 x 4*BT) when every replica of the launch has that
+// shape; the general path otherwise.
+template <int MODE>
+static void tile_dispatch(const Launch &lc, hipStream_t s)
+{
+    if (MODE != M_PLANES && lc.uniform_th == 64 && lc.uniform_tw == 64)
+        tile_dispatch_bt<MODE, 16>(lc, s);
+    else if (MODE != M_PLANES && lc.uniform_th == 32 && lc.uniform_tw == 64)
+        tile_dispatch_bt<MODE, 8>(lc, s);
+    else if (MODE != M_PLANES && lc.uniform_th == 16 && lc.uniform_tw == 64)
+        tile_dispatch_bt<MODE, 4>(lc, s);
+    else
+        tile_dispatch_bt<MODE, 0>(lc, s);
+}
+
+hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
+{
+    switch (mode) {
+    case TILE_BONDS: tile_dispatch<M_BONDS>(lc, s); break;
+    case TILE_FLIP: tile_dispatch<M_FLIP>(lc, s); break;
+    case TILE_FUSED: tile_dispatch<M_FUSED>(lc, s); break;
+    case TILE_PLANES: tile_dispatch<M_PLANES>(lc, s); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -832,36 +883,34 @@ hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s)
 {
     const int64_t waves = 2 * (lc.gtile_end - lc.gtile0);
     const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves)), block(kThreads);
-    if (lc.label_bits == 64)
-        hipLaunchKernelGGL((k_merge<unsigned long long>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
-    else
-        hipLaunchKernelGGL((k_merge<uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
-    return hipGetLastError();
-}
-
-hipError_t launch_flip(const Launch &lc, const FlipArgs &fa, hipStream_t s)
-{
-    const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
-    if (lc.label_bits == 64)
-        hipLaunchKernelGGL((k_flip<unsigned long long>), grid, block, lds_flip<unsigned long long>(lc.max_th), s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, fa);
-    else
-        hipLaunchKernelGGL((k_flip<uint32_t>), grid, block, lds_flip<uint32_t>(lc.max_th), s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, fa);
+    if (lc.label_bits == 64) {
+        if (lc.big_index)
+            hipLaunchKernelGGL((k_merge<unsigned long long, uint64_t>), grid, block, 0, s, lc.reps, lc.tile_rep,
+                               lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
+        else
+            hipLaunchKernelGGL((k_merge<unsigned long long, uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep,
+                               lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
+    } else {
+        hipLaunchKernelGGL((k_merge<uint32_t, uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0,
+                           lc.gtile_end, (int32_t)next_dir);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_measure(const Launch &lc, hipStream_t s)
 {
     const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
-    if (lc.label_bits == 64)
-        hipLaunchKernelGGL((k_measure<unsigned long long>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+    if (lc.big_index)
+        hipLaunchKernelGGL((k_measure<uint64_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
     else
         hipLaunchKernelGGL((k_measure<uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out, hipStream_t s)
+hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)nrep), dim3(kThreads), 0, s, d_reps, fa, measure_out);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)nrep), dim3(kFinThreads), 0, s, d_reps, fa, measure_out);
     return hipGetLastError();
 }
 
@@ -870,13 +919,12 @@ hipError_t launch_flatten(const void *d_lab, int32_t label_bits, int64_t N, void
 {
     const int64_t blocks = (N + kThreads - 1) / kThreads;
     if (label_bits == 64)
-        hipLaunchKernelGGL((k_flatten<unsigned long long>), dim3((unsigned)blocks), dim3(kThreads), 0, s, (const unsigned long long *)d_lab, N, d_out, out_bits);
+        hipLaunchKernelGGL((k_flatten<unsigned long long>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           (const unsigned long long *)d_lab, N, d_out, out_bits);
     else
-        hipLaunchKernelGGL((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, (const uint32_t *)d_lab, N, d_out, out_bits);
+        hipLaunchKernelGGL((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           (const uint32_t *)d_lab, N, d_out, out_bits);
     return hipGetLastError();
 }
-
-size_t lds_bytes_bonds(int TH) { return lds_bonds(TH); }
-size_t lds_bytes_flip(int TH, int label_bits) { return label_bits == 64 ? lds_flip<unsigned long long>(TH) : lds_flip<uint32_t>(TH); }
 
 }  // namespace xy

@@ -17,8 +17,13 @@ struct Launch {
     int32_t nrep;
     int32_t label_bits;       // 32 or 64
     int32_t max_th;           // largest tile height among the replicas (LDS sizing)
+    int32_t big_index;        // 1: 64-bit site indices (some replica has N > 2^30)
+    int32_t uniform_tw, uniform_th;  // tile shape shared by every replica, or 0
     int64_t gtile0, gtile_end;
 };
+
+// Modes of the tile kernel.
+enum { TILE_BONDS = 0, TILE_FLIP = 1, TILE_FUSED = 2, TILE_PLANES = 3 };
 
 // Per-launch arguments of the flip kernel's finalisation (observables, PCC).
 struct FlipArgs {
@@ -37,15 +42,13 @@ struct FlipArgs {
 hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s);
 hipError_t launch_edge_refresh(const RepDesc *d_reps, int32_t r, int64_t ntiles, hipStream_t s);
 hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s);
-hipError_t launch_bonds(const Launch &lc, bool from_planes, hipStream_t s);
+hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s);
 hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s);
-hipError_t launch_flip(const Launch &lc, const FlipArgs &fa, hipStream_t s);
 hipError_t launch_measure(const Launch &lc, hipStream_t s);
 hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out,
                            hipStream_t s);
 hipError_t launch_flatten(const void *d_lab, int32_t label_bits, int64_t N, void *d_out, int32_t out_bits,
                           hipStream_t s);
-size_t lds_bytes_bonds(int TH);
-size_t lds_bytes_flip(int TH, int label_bits);
+size_t lds_bytes_tile(int TH, int label_bits);
 
 }  // namespace xy

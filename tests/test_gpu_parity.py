@@ -173,3 +173,29 @@ def test_full_size_l4096_one_sweep():
     # The bench configuration (L = 4096, beta = 1.12, default tiles): one sweep
     # checked element by element against the oracle.
     _trajectory(4096, 1.12, wl.SEED_L4096, nsweeps=1, state_seed=4096)
+
+
+@pytest.mark.parametrize("L,tile_rows,bits", [(8, 0, 0), (64, 32, 0), (256, 16, 0), (256, 64, 0), (128, 32, 64)])
+def test_fused_multi_sweep_parity(L, tile_rows, bits):
+    # one call of many sweeps: every sweep but the last runs the fused
+    # flip(t) + links(t+1) pass
+    xy = _gpu()
+    print("fused L=%d rows=%d bits=%d" % (L, tile_rows, bits), flush=True)
+    seed = 0xF05E + L
+    lat = xy.Lattices(dict(L=L, beta=1.12, seed=seed, tile_rows=tile_rows, label_bits=bits))
+    c0, s0 = wl.random_spins(L, 9 + L)
+    lat.set_state(c0, s0)
+    orc = oracle.Lattice(L=L, beta=1.12, seed=seed, storage32=True, c=c0.astype(np.float64),
+                         s=s0.astype(np.float64))
+    tr_g = lat.sweep(20, trace=True)
+    tr_o, ties_o = orc.run(19)
+    obs_o, t_o, bx_o, by_o, lab_o = orc.sweep_detail()
+    cg, sg = lat.get_state()
+    assert np.array_equal(cg.astype(np.float64), orc.c) and np.array_equal(sg.astype(np.float64), orc.s)
+    assert np.array_equal(lat.labels(), lab_o)
+    bx_g, by_g = lat.bonds()
+    assert np.array_equal(bx_g, bx_o) and np.array_equal(by_g, by_o)
+    for k, name in enumerate(NAMES):
+        assert np.max(np.abs(tr_g[:19, 0][name] - tr_o[:, k])) <= OBS_TOL, name
+        assert abs(float(tr_g[19, 0][name]) - obs_o[k]) <= OBS_TOL, name
+    lat.close()
