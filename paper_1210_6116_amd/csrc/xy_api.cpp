@@ -273,7 +273,10 @@ int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, bool *re
         HIPCHECK(h, hipEventRecord(sweep_begin, h->stream));
     }
     if (!*ready) HIPCHECK(h, timed(h, XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, h->stream); }));
-    HIPCHECK(h, timed(h, XY_K_MERGE, [&] { return xy::launch_merge(lc, true, h->stream); }));
+    HIPCHECK(h, timed(h, XY_K_MERGE, [&] {
+        hipError_t e = xy::launch_merge(lc, true, h->stream);
+        return e == hipSuccess ? xy::launch_compress(lc, h->stream) : e;
+    }));
     const bool fuse = fuse_next && h->plan.pingpong;
     if (fuse)
         HIPCHECK(h, timed(h, XY_K_FUSED, [&] { return xy::launch_tile(lc, xy::TILE_FUSED, h->stream); }));

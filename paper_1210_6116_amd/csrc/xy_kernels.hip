@@ -13,6 +13,7 @@
 //   k_merge        union of the labels across every active link that leaves a
 //                  tile (lock-free; the larger root is always hooked under the
 //                  smaller one, so every final root is its cluster's minimum site)
+//   k_merge<COMPRESS> end labels of edge links pointed at their final roots
 //   k_tile<FLIP>   root lookup, reflection of flipped clusters in FP64 with one
 //                  rounding to the FP32 state, the six link / site sums of the
 //                  flipped state
@@ -274,7 +275,7 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
 // ----------------------------------------------------------- the tile kernel
 // LDS: spin[(TH+1)*(TW+1)] float2 (tile + right halo column + bottom halo row)
 //      | bxm[64], bym[64] u64 row masks of active links
-//      | memo[TW*TH] (LT; FLIP) aliased by lab[TW*TH] (u32; labelling)
+//      | lab[TW*TH] u32 tile-local union-find (labelling)
 // BT = rows per wave known at compile time (tiles of 64 x 4*BT; every loop
 // over a wave's rows is unrolled and its independent loads are issued
 // together); BT = 0 is the general path for lattices narrower than 64.
@@ -309,8 +310,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     float2 *spin = (float2 *)smem;
     uint64_t *bxm = (uint64_t *)(spin + (TH + 1) * SS);
     uint64_t *bym = bxm + 64;
-    LT *memo = (LT *)(bym + 64);
-    uint32_t *lab_s = (uint32_t *)memo;
+    uint32_t *lab_s = (uint32_t *)(bym + 64);
     const int64_t ecount = TH + TW;
     float *__restrict__ cp = R.c;
     float *__restrict__ sp = R.s;
@@ -320,7 +320,6 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
         const uint32_t *__restrict__ coins = R.coins[par];
         const double rx = st->dir[par][0], ry = st->dir[par][1];
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
-        const LT UNK = ~(LT)0;
         auto flip_one = [&](uint32_t coinword, LT root, float c0, float s0, float &c1, float &s1) -> bool {
             const bool f = (coinword >> (root & 31)) & 1u;
             double c = c0, s = s0;
@@ -338,7 +337,8 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
             s1 = (float)s;
             return f || renorm;
         };
-        // all independent loads of the wave's rows first: parents and spins
+        // all independent loads of the wave's rows first: parents and spins;
+        // after the merge's compression pass the root of site i is lab[lab[i]]
         LT pl[BMAX];
         float c0[BMAX], s0[BMAX];
 #pragma unroll
@@ -350,67 +350,37 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
                 s0[k] = sp[i];
             }
         }
-        // Phase A: roots of clusters that leave the tile are resolved now
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-            if (own(k)) {
-                const IT i = T.site(yb + k, lane);
-                const LT p = pl[k];
-                LT m = UNK;
-                if (p == (LT)i)
-                    m = p;
-                else if (!T.contains((IT)p))
-                    m = find_jump(lab, p);
-                memo[(yb + k) * TW + lane] = m;
-            }
-        }
         // halo: right column and bottom row of the neighbouring tiles (spins
         // before the sweep from their edge copies), flipped here exactly as
         // their owners flip them
+        LT hp = 0;
+        float2 he = make_float2(0.f, 0.f);
+        int hslot = -1;
         if (wave == 0 && lane < TH) {
             const IT h = ((T.y0 + (IT)lane) << T.log2L) + ((T.x0 + (IT)TW) & Lm);
-            const float2 e = R.edge[par][T.right_tile() * ecount + lane];
-            const LT root = find_jump(lab, (LT)h);
-            float c1, s1;
-            flip_one(coins[root >> 5], root, e.x, e.y, c1, s1);
-            spin[lane * SS + TW] = make_float2(c1, s1);
+            hp = lab[h];
+            he = R.edge[par][T.right_tile() * ecount + lane];
+            hslot = lane * SS + TW;
         } else if (wave == 1 && lane < TW) {
             const IT h = (((T.y0 + (IT)TH) & Lm) << T.log2L) + T.x0 + (IT)lane;
-            const float2 e = R.edge[par][T.down_tile() * ecount + TH + lane];
-            const LT root = find_jump(lab, (LT)h);
-            float c1, s1;
-            flip_one(coins[root >> 5], root, e.x, e.y, c1, s1);
-            spin[TH * SS + lane] = make_float2(c1, s1);
+            hp = lab[h];
+            he = R.edge[par][T.down_tile() * ecount + TH + lane];
+            hslot = TH * SS + lane;
         }
-        __syncthreads();
-        // Phase B: roots of the remaining sites via the tile memo, coins, flip
         LT root[BMAX];
-        uint32_t cw[BMAX];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            if (own(k)) {
-                LT rt = memo[(yb + k) * TW + lane];
-                if (rt == UNK) {
-                    LT x = pl[k];
-                    while (true) {
-                        if (!T.contains((IT)x)) {
-                            rt = find_jump(lab, x);
-                            break;
-                        }
-                        const LT m = memo[T.local((IT)x)];
-                        if (m != UNK) {
-                            rt = m;
-                            break;
-                        }
-                        x = lab[x];
-                    }
-                }
-                root[k] = rt;
-            }
-        }
+        for (int k = 0; k < B; ++k)
+            if (own(k)) root[k] = lab[pl[k]];
+        const LT hroot = hslot >= 0 ? lab[hp] : 0;
+        uint32_t cw[BMAX];
 #pragma unroll
         for (int k = 0; k < B; ++k)
             if (own(k)) cw[k] = coins[root[k] >> 5];
+        if (hslot >= 0) {
+            float c1, s1;
+            flip_one(coins[hroot >> 5], hroot, he.x, he.y, c1, s1);
+            spin[hslot] = make_float2(c1, s1);
+        }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             if (own(k)) {
@@ -623,7 +593,12 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
 // One wave per (tile, edge): edge 0 = links leaving the right column, edge 1 =
 // links leaving the bottom row.  Also computes the mirror direction of the
 // next sweep (tile 0 of each replica).
-template <typename LT, typename IT>
+// COMPRESS (a second launch, after every union has finished): both end sites
+// of every active edge link and the labels read from them are pointed straight
+// at their final root.  Every tile-local root of a cluster that crosses a tile
+// edge is such an end site or end label, so afterwards the root of any site i
+// is lab[lab[i]].
+template <typename LT, typename IT, bool COMPRESS>
 __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ reps,
                                                      const uint32_t *__restrict__ tile_rep,
                                                      int32_t nrep, int64_t gtile0, int64_t gtile_end,
@@ -665,9 +640,32 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
     }
     const LT pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
     const int pon = __shfl_up((int)on, 1);
-    const bool dup = lane > 0 && pon && pa == a && pb == b;
-    if (on && !dup) union_global(lab, a, b);
-    if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
+    // the union of a pair equal to the previous lane's is skipped; the
+    // compression pass visits every link, because two different hooked
+    // tile-local roots can read back the same parent
+    const bool dup = !COMPRESS && lane > 0 && pon && pa == a && pb == b;
+    if (on && !dup) {
+        if (COMPRESS) {
+            // The end sites themselves are re-pointed as well: a site that is
+            // its tile-local root and was hooked reads back its new parent.
+            // Writes are atomic minima: the root is the smallest site of its
+            // tree, so a concurrent write of a mere ancestor can never
+            // replace it.
+            LT root = (LT)i;
+            while (true) {
+                const LT p = lab[root];
+                if (p == root) break;
+                root = p;
+            }
+            if (lab[i] != root) atomicMin(&lab[i], root);
+            if (lab[a] != root) atomicMin(&lab[a], root);
+            if (lab[j] != root) atomicMin(&lab[j], root);
+            if (lab[b] != root) atomicMin(&lab[b], root);
+        } else {
+            union_global(lab, a, b);
+        }
+    }
+    if (!COMPRESS && next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
 }
 
 // ------------------------------------------------- finalise a sweep
@@ -811,8 +809,8 @@ __global__ __launch_bounds__(kThreads) void k_flatten(const LT *__restrict__ lab
 // ====================================================== host-side launchers
 size_t lds_bytes_tile(int TH, int label_bits)
 {
-    const size_t memo = (size_t)64 * TH * (label_bits == 64 ? 8 : 4);
-    return (size_t)(TH + 1) * 65 * sizeof(float2) + 2 * 64 * sizeof(uint64_t) + memo;
+    (void)label_bits;
+    return (size_t)(TH + 1) * 65 * sizeof(float2) + 2 * 64 * sizeof(uint64_t) + (size_t)64 * TH * sizeof(uint32_t);
 }
 
 hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s)
@@ -879,21 +877,33 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s)
+template <bool COMPRESS>
+static void merge_dispatch(const Launch &lc, bool next_dir, hipStream_t s)
 {
     const int64_t waves = 2 * (lc.gtile_end - lc.gtile0);
     const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves)), block(kThreads);
     if (lc.label_bits == 64) {
         if (lc.big_index)
-            hipLaunchKernelGGL((k_merge<unsigned long long, uint64_t>), grid, block, 0, s, lc.reps, lc.tile_rep,
-                               lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
+            hipLaunchKernelGGL((k_merge<unsigned long long, uint64_t, COMPRESS>), grid, block, 0, s, lc.reps,
+                               lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
         else
-            hipLaunchKernelGGL((k_merge<unsigned long long, uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep,
-                               lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
+            hipLaunchKernelGGL((k_merge<unsigned long long, uint32_t, COMPRESS>), grid, block, 0, s, lc.reps,
+                               lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
     } else {
-        hipLaunchKernelGGL((k_merge<uint32_t, uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0,
-                           lc.gtile_end, (int32_t)next_dir);
+        hipLaunchKernelGGL((k_merge<uint32_t, uint32_t, COMPRESS>), grid, block, 0, s, lc.reps, lc.tile_rep,
+                           lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
     }
+}
+
+hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s)
+{
+    merge_dispatch<false>(lc, next_dir, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress(const Launch &lc, hipStream_t s)
+{
+    merge_dispatch<true>(lc, false, s);
     return hipGetLastError();
 }
 
