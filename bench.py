@@ -94,6 +94,101 @@ def cpu_baseline(L: int, beta: float, seed: int, nsweeps: int):
             "host_cpus": os.cpu_count()}
 
 
+def bench_l65536(sweeps: int):
+    """Generalized-PCC run of one L = 65536 lattice (64-bit labels), beta0 = 1.0,
+    window 1, dbeta 0.004 halved every 250 steps down to 0.0005."""
+    import torch
+    import paper_1210_6116_amd as xy
+    import xyworkloads as wl
+
+    L = 65536
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    lat = xy.Lattices(dict(L=L, beta=1.0, seed=wl.SEED_L65536, label_bits=64), stream=stream)
+    torch.cuda.synchronize()
+    t_alloc = time.perf_counter() - t0
+    lat.pcc(2, 1, 0.004, dbeta_min=0.0005, halve_every=250)  # warm-up steps
+    torch.cuda.synchronize()
+    lat.timing(True)
+    t0 = time.perf_counter()
+    lat.pcc(sweeps, 1, 0.004, dbeta_min=0.0005, halve_every=250)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, n, per = lat.timing_read(sweeps)
+    lat.timing(False)
+    beta = lat.beta()
+    arena_gb = lat.bytes / 1e9
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    per = list(per)
+    return {"workload": "PCC run, L=65536, uint64 labels, beta0=1.0, window 1, dbeta 0.004 halved every "
+                        "250 steps (floor 0.0005); %d timed sweeps after 2" % sweeps,
+            "value": sweeps * L * L / dt, "unit": "spin updates/s", "ms_per_sweep": dt / sweeps * 1e3,
+            "sweep_ms_p50": percentile(per, 50), "sweep_ms_p99": percentile(per, 99),
+            "kernels_ms": {k: ms[i] / n[i] for i, k in enumerate(xy._lib.KERNEL_NAMES) if n[i] and k != "sweep"},
+            "beta_after": beta, "arena_GB": arena_gb, "alloc_init_s": t_alloc}
+
+
+def bench_batched(sweeps: int, nrep: int = 512):
+    """512 replicas of log-uniform L in 64..2048 and beta in [1.0, 1.2]: all in
+    one handle (one launch per kernel per sweep, replayed from a HIP graph)
+    against the same replicas swept one after another through plain handles."""
+    import torch
+    import paper_1210_6116_amd as xy
+    import xyworkloads as wl
+
+    specs = wl.batched_replicas(nrep)
+    total = sum(sp["L"] ** 2 for sp in specs)
+    chunk = 10 if sweeps % 10 == 0 else 1
+    stream = torch.cuda.Stream()
+    bat = xy.Lattices(specs, stream=stream)
+    bat.sweep_graph(chunk, 1)  # capture + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bat.sweep_graph(chunk, sweeps // chunk)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    bat.close()
+    del bat
+    plain = [xy.Lattices(sp, stream=stream) for sp in specs]
+    for lat in plain:
+        lat.sweep(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in plain:
+        lat.sweep(sweeps)
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t0
+    for lat in plain:
+        lat.close()
+    del plain
+    torch.cuda.empty_cache()
+    return {"workload": "%d replicas, L log-uniform over 64..2048, beta uniform on [1.0, 1.2], %d timed sweeps "
+                        "each; batched = one handle replayed from a %d-sweep HIP graph; plain = one handle per "
+                        "replica, swept one after another" % (nrep, sweeps, chunk),
+            "spins": total, "batched_value": sweeps * total / dt_b, "plain_value": sweeps * total / dt_p,
+            "unit": "spin updates/s", "speedup": dt_p / dt_b}
+
+
+def bench_serving(n_requests: int, sweeps_lo: int, sweeps_hi: int):
+    """Poisson (20/s) stream of PCC run requests, L = 256..8192, admitted by a
+    200 GB HBM budget and 64 slots, served by continuous batching."""
+    import xyworkloads as wl
+    from paper_1210_6116_amd.serve import serve
+
+    trace = wl.serving_trace(n_requests=n_requests, sweeps_lo=sweeps_lo, sweeps_hi=sweeps_hi)
+    res = serve(trace, budget_bytes=200 * 10 ** 9, max_slots=64, round_sweeps=16)
+    s = res["summary"]
+    offered = s["offered_updates"] / (max(r["arrival"] for r in trace) + 1e-9)
+    return {"workload": "%d requests, Poisson rate 20/s, L = 2^(8..13), %d-%d sweeps each (the full trace has "
+                        "200 requests of 1000-10000 sweeps), PCC window 1, 200 GB budget, 64 slots"
+                        % (n_requests, sweeps_lo, sweeps_hi),
+            "served_value": s["served_updates_per_s"], "unit": "spin updates/s",
+            "ttc_p50_s": s["ttc_p50_s"], "ttc_p99_s": s["ttc_p99_s"], "makespan_s": s["makespan_s"],
+            "mean_running": s["mean_running"], "offered_updates_per_s": offered}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +200,11 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
     ap.add_argument("--no-instrument", action="store_true", help="skip the instrumented pass")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the L=65536 PCC, batched and serving legs")
+    ap.add_argument("--l65536-sweeps", type=int, default=100)
+    ap.add_argument("--batched-sweeps", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -194,6 +294,18 @@ def main():
         "latency": latency,
         "kernels": kernels,
     }
+    if not args.no_extras:
+        extras = {}
+        for name, fn in (("L65536_pcc", lambda: bench_l65536(args.l65536_sweeps)),
+                         ("batched_vs_plain", lambda: bench_batched(args.batched_sweeps)),
+                         ("serving", lambda: bench_serving(args.serve_requests, 200, 2000))):
+            print("bench: %s" % name, file=sys.stderr, flush=True)
+            try:
+                extras[name] = fn()
+            except Exception as exc:  # reported, not hidden: the headline line still prints
+                extras[name] = {"error": "%s: %s" % (type(exc).__name__, exc)}
+            print("bench: %s done" % name, file=sys.stderr, flush=True)
+        line["extras"] = extras
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)

@@ -105,6 +105,13 @@ int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_
  * trace[k * n + rep] with the observables after sweep k (synchronizes). */
 int xy_sweep(xy_handle *h, int64_t nsweeps, xy_obs *trace);
 
+/* Runs replays x nsweeps sweeps: the launch sequence of nsweeps sweeps is
+ * captured once into a HIP graph on the handle's stream (kept in the handle and
+ * reused while nsweeps stays the same) and the graph is launched replays times.
+ * Same results as xy_sweep(h, replays * nsweeps, NULL); asynchronous.  Not
+ * allowed while per-kernel timing is on (XY_ESTATE). */
+int xy_sweep_graph(xy_handle *h, int64_t nsweeps, int64_t replays);
+
 /* Observables of every replica's current configuration (n xy_obs, host;
  * synchronizes).  near_ties is 0; sweep is the replica's sweep count. */
 int xy_measure(xy_handle *h, xy_obs *out);
@@ -167,6 +174,41 @@ enum {
 int xy_timing(xy_handle *h, int32_t enable);
 int xy_timing_read(xy_handle *h, double *ms, int64_t *launches, double *samples, int64_t cap,
                    int64_t *nsamples);
+
+/* ---- serving: continuous batching of PCC runs ------------------------------
+ * A group keeps up to max_slots requests (each one lattice with its own L,
+ * seed and initial beta, and a number of sweeps to run) resident in one device
+ * arena of budget_bytes, and advances all resident requests together: every
+ * round runs the same number of sweeps of each of them in the same kernel
+ * launches, each sweep followed by its own PCC update with the group's rule c.
+ * A request's result does not depend on the other requests in the group.
+ * Requests are admitted between rounds as slots and memory free up. */
+typedef struct xy_group xy_group;
+
+/* budget_bytes: device memory the group may use (one arena, allocated here);
+ * max_slots >= 1; c: PCC rule of every request; hip_stream as in xy_alloc. */
+int xy_group_create(size_t budget_bytes, int32_t max_slots, const xy_pcc *c, void *hip_stream,
+                    xy_group **out);
+/* Admits a request of nsweeps >= 1 sweeps (label_bits must resolve to 32).
+ * *slot receives its slot id.  XY_EBUDGET if no slot or not enough free
+ * memory right now (nothing changes); XY_EINVAL for bad parameters. */
+int xy_group_add(xy_group *g, const xy_params *p, int64_t nsweeps, int32_t *slot);
+/* Bytes a request of these parameters occupies in the group's arena. */
+int xy_group_bytes(const xy_params *p, size_t *bytes);
+/* Runs one round of min(max_sweeps, fewest remaining sweeps) sweeps of every
+ * running request (0 if none is running); *ran receives that number.
+ * Synchronizes. */
+int xy_group_round(xy_group *g, int64_t max_sweeps, int64_t *ran);
+/* Slot ids of requests that finished since the previous call (up to cap). */
+int xy_group_poll(xy_group *g, int32_t *slots, int32_t cap, int32_t *n);
+/* Result of a finished (or running) request: observables after its latest
+ * sweep, its current beta, and the mean of beta over its PCC steps. */
+int xy_group_result(xy_group *g, int32_t slot, xy_obs *last, double *beta, double *beta_mean);
+/* Frees a finished request's slot and memory. */
+int xy_group_release(xy_group *g, int32_t slot);
+/* Bytes in use and running requests. */
+int xy_group_info(xy_group *g, size_t *used_bytes, int32_t *running);
+int xy_group_free(xy_group *g);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *xy_last_error(void);

@@ -67,6 +67,10 @@ class Lattices:
         _lib.xy_sweep(self.h, nsweeps, out)
         return out
 
+    def sweep_graph(self, nsweeps: int, replays: int):
+        """replays x nsweeps sweeps from one captured HIP graph of nsweeps sweeps."""
+        _lib.xy_sweep_graph(self.h, nsweeps, replays)
+
     def measure(self):
         out = np.zeros(self.n, dtype=OBS_DTYPE)
         _lib.xy_measure(self.h, out)

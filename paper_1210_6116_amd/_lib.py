@@ -59,6 +59,7 @@ _SIGS = {
     "xy_alloc": (ctypes.c_int, [_P(xy_params), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_size_t, _P(ctypes.c_void_p)]),
     "xy_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "xy_sweep_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]),
     "xy_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "xy_pcc_step": (ctypes.c_int, [ctypes.c_void_p, _P(xy_pcc), ctypes.c_int64, ctypes.c_void_p]),
     "xy_free": (ctypes.c_int, [ctypes.c_void_p]),
@@ -75,6 +76,17 @@ _SIGS = {
     "xy_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_int64, _P(ctypes.c_int64)]),
     "xy_last_error": (ctypes.c_char_p, []),
+    "xy_group_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, _P(xy_pcc), ctypes.c_void_p,
+                                       _P(ctypes.c_void_p)]),
+    "xy_group_add": (ctypes.c_int, [ctypes.c_void_p, _P(xy_params), ctypes.c_int64, _P(ctypes.c_int32)]),
+    "xy_group_bytes": (ctypes.c_int, [_P(xy_params), _P(ctypes.c_size_t)]),
+    "xy_group_round": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _P(ctypes.c_int64)]),
+    "xy_group_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int32)]),
+    "xy_group_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, _P(ctypes.c_double),
+                                       _P(ctypes.c_double)]),
+    "xy_group_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "xy_group_info": (ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_size_t), _P(ctypes.c_int32)]),
+    "xy_group_free": (ctypes.c_int, [ctypes.c_void_p]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -120,6 +132,10 @@ def xy_alloc(params, stream=None, arena=None, arena_bytes=0):
 
 def xy_sweep(h, nsweeps: int, trace: np.ndarray | None = None):
     _check(load().xy_sweep(h, nsweeps, None if trace is None else _ptr(trace)))
+
+
+def xy_sweep_graph(h, nsweeps: int, replays: int):
+    _check(load().xy_sweep_graph(h, nsweeps, replays))
 
 
 def xy_measure(h, out: np.ndarray):
@@ -187,3 +203,63 @@ def xy_timing_read(h, max_samples: int = 0):
 
 def xy_last_error() -> str:
     return load().xy_last_error().decode()
+
+
+# ------------------------------------------------- serving group
+def xy_group_create(budget_bytes: int, max_slots: int, pcc: xy_pcc, stream=None):
+    g = ctypes.c_void_p()
+    _check(load().xy_group_create(budget_bytes, max_slots, ctypes.byref(pcc), stream, ctypes.byref(g)))
+    return g
+
+
+def xy_group_bytes(params: xy_params) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().xy_group_bytes(ctypes.byref(params), ctypes.byref(out)))
+    return out.value
+
+
+def xy_group_add(g, params: xy_params, nsweeps: int):
+    """Slot id, or None when the request does not fit right now (XY_EBUDGET)."""
+    slot = ctypes.c_int32(-1)
+    rc = load().xy_group_add(g, ctypes.byref(params), nsweeps, ctypes.byref(slot))
+    if rc == XY_EBUDGET:
+        return None
+    _check(rc)
+    return slot.value
+
+
+def xy_group_round(g, max_sweeps: int) -> int:
+    ran = ctypes.c_int64(0)
+    _check(load().xy_group_round(g, max_sweeps, ctypes.byref(ran)))
+    return ran.value
+
+
+def xy_group_poll(g, cap: int = 1024):
+    out = np.zeros(cap, dtype=np.int32)
+    n = ctypes.c_int32(0)
+    _check(load().xy_group_poll(g, _ptr(out), cap, ctypes.byref(n)))
+    return [int(v) for v in out[:n.value]]
+
+
+def xy_group_result(g, slot: int):
+    """(observables after the latest sweep, beta, mean beta over PCC steps)."""
+    last = np.zeros(1, dtype=OBS_DTYPE)
+    beta = ctypes.c_double(0.0)
+    mean = ctypes.c_double(0.0)
+    _check(load().xy_group_result(g, slot, _ptr(last), ctypes.byref(beta), ctypes.byref(mean)))
+    return last[0], beta.value, mean.value
+
+
+def xy_group_release(g, slot: int):
+    _check(load().xy_group_release(g, slot))
+
+
+def xy_group_info(g):
+    used = ctypes.c_size_t(0)
+    running = ctypes.c_int32(0)
+    _check(load().xy_group_info(g, ctypes.byref(used), ctypes.byref(running)))
+    return used.value, running.value
+
+
+def xy_group_free(g):
+    _check(load().xy_group_free(g))

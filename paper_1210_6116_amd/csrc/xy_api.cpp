@@ -8,14 +8,16 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
 #include "../../include/xy.h"
 #include "xy_device.hpp"
 #include "xy_launch.hpp"
+#include "xy_host.hpp"
 
-namespace {
+namespace xyhost {
 
 thread_local std::string g_err;
 
@@ -30,8 +32,6 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-constexpr size_t kAlign = 256;
-constexpr int64_t kTraceChunk = 256;  // sweeps (or PCC steps) per trace copy-back
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -42,25 +42,8 @@ int ilog2(int64_t v)
     return k;
 }
 
-struct Resolved {
-    int64_t L, N;
-    int32_t TW, TH, ntx, nty;
-    int64_t ntiles;
-};
 
-// Per-replica byte layout inside the arena.
-struct RepLayout {
-    size_t c, s, lab[2], bx[2], by[2], coins[2], edge[2], partials, end;
-};
 
-struct Plan {
-    int32_t n = 0, label_bits = 32, max_th = 1, uniform_tw = -1, uniform_th = -1;
-    bool pingpong = true, big_index = false;
-    std::vector<Resolved> res;
-    std::vector<RepLayout> lay;
-    size_t off_reps = 0, off_state = 0, off_tile_rep = 0, off_obs = 0, total = 0;
-    int64_t total_tiles = 0;
-};
 
 int check_params(const xy_params *p, int32_t n)
 {
@@ -101,7 +84,10 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
     if (want32 && (need64 || want64)) return fail(XY_EINVAL, "replicas disagree on the label width");
     P.label_bits = (need64 || want64) ? 64 : 32;
     P.pingpong = maxN < (int64_t(1) << 30);
-    P.big_index = maxN > (int64_t(1) << 30);
+    // 64-bit site indices are needed above 2^30 sites; XY_WIDE_INDEX=1 selects
+    // them for any size (the same kernels with wider index arithmetic; tests)
+    const char *wide = std::getenv("XY_WIDE_INDEX");
+    P.big_index = maxN > (int64_t(1) << 30) || (wide && wide[0] == '1');
     const int lb = P.label_bits / 8;
     size_t off = 0;
     P.res.resize(n);
@@ -166,7 +152,41 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
     return XY_OK;
 }
 
-}  // namespace
+void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepState *st, int64_t tile_base,
+               int32_t idx, xy::RepDesc &d)
+{
+    const Resolved &r = P.res[k];
+    const RepLayout &l = P.lay[k];
+    std::memset(&d, 0, sizeof d);
+    d.c = reinterpret_cast<float *>(A + l.c);
+    d.s = reinterpret_cast<float *>(A + l.s);
+    for (int q = 0; q < 2; ++q) {
+        d.lab[q] = A + l.lab[q];
+        d.bx[q] = reinterpret_cast<uint32_t *>(A + l.bx[q]);
+        d.by[q] = reinterpret_cast<uint32_t *>(A + l.by[q]);
+        d.edge[q] = reinterpret_cast<float2 *>(A + l.edge[q]);
+        d.coins[q] = reinterpret_cast<uint32_t *>(A + l.coins[q]);
+    }
+    d.partials = reinterpret_cast<double *>(A + l.partials);
+    d.st = st;
+    d.L = r.L;
+    d.N = r.N;
+    d.ntiles = r.ntiles;
+    d.tile_base = tile_base;
+    d.seed = p.seed;
+    d.rep = p.replica;
+    d.log2L = ilog2(r.L);
+    d.TW = r.TW;
+    d.TH = r.TH;
+    d.log2TW = ilog2(r.TW);
+    d.ntx = r.ntx;
+    d.nty = r.nty;
+    d.idx = idx;
+}
+
+}  // namespace xyhost
+
+using namespace xyhost;
 
 struct xy_handle {
     Plan plan;
@@ -190,6 +210,10 @@ struct xy_handle {
     std::vector<hipEvent_t> ev_pool;
     double ms[XY_K_COUNT] = {};
     int64_t launches[XY_K_COUNT] = {};
+    // captured sweep sequence (xy_sweep_graph)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int64_t graph_n = 0;
 };
 
 namespace {
@@ -272,19 +296,8 @@ int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, bool *re
         HIPCHECK(h, take_event(h, &sweep_begin));
         HIPCHECK(h, hipEventRecord(sweep_begin, h->stream));
     }
-    if (!*ready) HIPCHECK(h, timed(h, XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, h->stream); }));
-    HIPCHECK(h, timed(h, XY_K_MERGE, [&] {
-        hipError_t e = xy::launch_merge(lc, true, h->stream);
-        return e == hipSuccess ? xy::launch_compress(lc, h->stream) : e;
-    }));
-    const bool fuse = fuse_next && h->plan.pingpong;
-    if (fuse)
-        HIPCHECK(h, timed(h, XY_K_FUSED, [&] { return xy::launch_tile(lc, xy::TILE_FUSED, h->stream); }));
-    else
-        HIPCHECK(h, timed(h, XY_K_FLIP, [&] { return xy::launch_tile(lc, xy::TILE_FLIP, h->stream); }));
-    HIPCHECK(h, timed(h, XY_K_FINALIZE,
-                      [&] { return xy::launch_finalize(h->d_reps, h->plan.n, fa, nullptr, h->stream); }));
-    *ready = fuse;
+    auto timer = [&](int kind, auto launch) { return timed(h, kind, launch); };
+    HIPCHECK(h, enqueue_sweep_lc(lc, h->d_reps, h->plan.n, h->plan.pingpong, fa, fuse_next, ready, h->stream, timer));
     if (h->timing) {
         xy_handle::Ev ev;
         ev.kind = XY_K_SWEEP;
@@ -393,34 +406,7 @@ int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_
     int64_t base = 0;
     for (int32_t k = 0; k < n; ++k) {
         const Resolved &r = P.res[k];
-        const RepLayout &l = P.lay[k];
-        xy::RepDesc &d = h->reps[k];
-        std::memset(&d, 0, sizeof d);
-        d.c = reinterpret_cast<float *>(A + l.c);
-        d.s = reinterpret_cast<float *>(A + l.s);
-        for (int q = 0; q < 2; ++q) {
-            d.lab[q] = A + l.lab[q];
-            d.bx[q] = reinterpret_cast<uint32_t *>(A + l.bx[q]);
-            d.by[q] = reinterpret_cast<uint32_t *>(A + l.by[q]);
-            d.edge[q] = reinterpret_cast<float2 *>(A + l.edge[q]);
-        }
-        d.coins[0] = reinterpret_cast<uint32_t *>(A + l.coins[0]);
-        d.coins[1] = reinterpret_cast<uint32_t *>(A + l.coins[1]);
-        d.partials = reinterpret_cast<double *>(A + l.partials);
-        d.st = h->d_state + k;
-        d.L = r.L;
-        d.N = r.N;
-        d.ntiles = r.ntiles;
-        d.tile_base = base;
-        d.seed = p[k].seed;
-        d.rep = p[k].replica;
-        d.log2L = ilog2(r.L);
-        d.TW = r.TW;
-        d.TH = r.TH;
-        d.log2TW = ilog2(r.TW);
-        d.ntx = r.ntx;
-        d.nty = r.nty;
-        d.idx = k;
+        fill_desc(P, k, p[k], A, h->d_state + k, base, k, h->reps[k]);
         for (int64_t tt = 0; tt < r.ntiles && n > 1; ++tt) tile_rep[base + tt] = (uint32_t)k;
         base += r.ntiles;
         xy::RepState &s = states[k];
@@ -451,6 +437,8 @@ int xy_free(xy_handle *h)
         (void)hipEventDestroy(e.b);
     }
     for (auto &e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->own_arena && h->arena) (void)hipFree(h->arena);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -479,6 +467,33 @@ int xy_sweep(xy_handle *h, int64_t nsweeps, xy_obs *trace)
             HIPCHECK(h, hipStreamSynchronize(h->stream));
         }
     }
+    return XY_OK;
+}
+
+int xy_sweep_graph(xy_handle *h, int64_t nsweeps, int64_t replays)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (nsweeps < 1 || replays < 0)
+        return fail(XY_EINVAL, "nsweeps=%lld replays=%lld", (long long)nsweeps, (long long)replays);
+    if (h->timing) return fail(XY_ESTATE, "per-kernel timing is on; graphs capture no events");
+    if (!h->graph_exec || h->graph_n != nsweeps) {
+        if (h->graph_exec) HIPCHECK(h, hipGraphExecDestroy(h->graph_exec));
+        if (h->graph) HIPCHECK(h, hipGraphDestroy(h->graph));
+        h->graph_exec = nullptr;
+        h->graph = nullptr;
+        HIPCHECK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+        bool ready = false;
+        for (int64_t k = 0; k < nsweeps && rc == XY_OK; ++k) rc = enqueue_sweep(h, no_pcc(h), k + 1 < nsweeps, &ready);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->stream, &graph);
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+        h->graph = graph;
+        HIPCHECK(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+        h->graph_n = nsweeps;
+    }
+    for (int64_t r = 0; r < replays; ++r) HIPCHECK(h, hipGraphLaunch(h->graph_exec, h->stream));
     return XY_OK;
 }
 

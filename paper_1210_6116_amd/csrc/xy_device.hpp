@@ -69,6 +69,8 @@ struct RepState {
     int64_t acc_n;           // sweeps in the running window
     int64_t pcc_k;           // PCC steps taken (halving schedule)
     uint64_t ties_total;
+    double beta_sum;         // sum of beta after each PCC step
+    int64_t beta_n;          // PCC steps summed
     xy_obs last;             // observables after the latest sweep
 };
 

@@ -115,6 +115,21 @@ __device__ __forceinline__ bool bond_decide(const BondCtx &B, float ai, float aj
     return e < omu;
 }
 
+// Inclusive prefix maximum over the 64 lanes of a wave with DPP moves:
+// shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the last lane of
+// row 0 (2) into row 1 (3), then the last lane of row 1 into rows 2 and 3.
+// Lanes without a source keep 0, the identity of the maximum of unsigned keys.
+__device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
 // ------------------------------------------------------- union-find in LDS
 __device__ __forceinline__ uint32_t lds_load(const uint32_t *p)
 {
@@ -552,23 +567,47 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     // ---- in-tile labelling of sweep tb
     const uint64_t twmask = TW == 64 ? ~0ull : ((1ull << TW) - 1ull);
     const uint64_t inner = twmask >> 1;  // link x -> x+1 stays inside the tile
-    // 1) row runs: each site points at the first site of its run of x-links
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-        if (own(k)) {
-            const int y = yb + k;
-            const uint64_t breaks = ~(bxm[y] & inner) & ((1ull << lane) - 1ull);
-            const int start = breaks ? 64 - __clzll((long long)breaks) : 0;
-            lab_s[y * TW + lane] = (uint32_t)(y * TW + start);
-        }
-    }
-    __syncthreads();
-    // 2) vertical links inside the tile; a link whose left neighbour joins the
-    //    same two runs is skipped
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t NONE = 0xFFFFFFFFu;
+    // 1) each wave scans its band of rows top-down.  A run of x-links takes
+    //    the smallest label among the runs above that it touches through a
+    //    y-link (segmented prefix minimum over the run's lanes, then read at
+    //    the run's last lane); a run touching two different labels records
+    //    their union; a run touching none is labelled by its first site.
+    //    Labels are sites of this band only, so the waves do not interact.
+    uint32_t lprev = NONE;
 #pragma unroll
     for (int k = 0; k < B; ++k) {
         const int y = yb + k;
-        if (own(k) && y < TH - 1) {
+        if (!FIXED && y >= TH) break;
+        const bool act = FIXED || lane < TW;
+        const uint64_t xm = bxm[y] & inner;
+        const uint64_t brk = ~xm & below;
+        const int start = brk ? 64 - __clzll((long long)brk) : 0;
+        const int end = __ffsll((long long)(~xm & ~below)) - 1;
+        uint32_t cand = NONE;
+        if (k > 0 && act && ((bym[y - 1] >> lane) & 1ull)) cand = lprev;
+        // segmented minimum as an unsegmented maximum of (run index, 0xFFFF - label):
+        // run indices grow with the lane, so a lane's prefix maximum comes from
+        // its own run; labels of a tile are below 2^12
+        const uint32_t run_id = (uint32_t)__popcll(brk);
+        const uint32_t key = (run_id << 16) | (0xFFFFu - (cand == NONE ? 0xFFFFu : cand));
+        const uint32_t pm = __shfl(wave_prefix_max(key), end & 63);
+        const uint32_t low = 0xFFFFu - (pm & 0xFFFFu);
+        const uint32_t m = low == 0xFFFFu ? NONE : low;
+        const uint32_t lab = m != NONE ? m : (uint32_t)(y * TW + start);
+        if (act) {
+            lab_s[y * TW + lane] = lab;
+            if (cand != NONE && cand != m) union_lds(lab_s, cand, m);
+        }
+        lprev = lab;
+    }
+    __syncthreads();
+    // 2) the seams between bands: y-links from a wave's last row; a link
+    //    whose left neighbour joins the same two runs is skipped
+    {
+        const int y = yb + B - 1;
+        if (y < TH - 1 && (FIXED || lane < TW)) {
             const uint64_t vv = bym[y] & twmask;
             const uint64_t h0 = bxm[y] & inner, h1 = bxm[y + 1] & inner;
             const uint64_t need = vv & ~(vv & (vv << 1) & (h0 << 1) & (h1 << 1));
@@ -745,6 +784,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restr
                 fa.wmean[fa.wrow * fa.nrep + R.idx] = m;
             }
             st->beta = nb;
+            st->beta_sum += nb;
+            st->beta_n += 1;
             st->pcc_k += 1;
             for (int k = 0; k < 8; ++k) acc[k] = 0.0;
             st->acc_n = 0;

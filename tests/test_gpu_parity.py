@@ -199,3 +199,15 @@ def test_fused_multi_sweep_parity(L, tile_rows, bits):
         assert np.max(np.abs(tr_g[:19, 0][name] - tr_o[:, k])) <= OBS_TOL, name
         assert abs(float(tr_g[19, 0][name]) - obs_o[k]) <= OBS_TOL, name
     lat.close()
+
+
+@pytest.mark.parametrize("L,nsweeps", [(64, 6), (256, 4)])
+def test_wide_index_path_parity(L, nsweeps, monkeypatch):
+    # the 64-bit site-index kernels that lattices above 2^30 sites use
+    monkeypatch.setenv("XY_WIDE_INDEX", "1")
+    _trajectory(L, 1.12, 0x91DE + L, nsweeps=nsweeps, label_bits=64, state_seed=5 + L)
+
+
+def test_wide_index_fused_parity(monkeypatch):
+    monkeypatch.setenv("XY_WIDE_INDEX", "1")
+    test_fused_multi_sweep_parity(128, 32, 64)
