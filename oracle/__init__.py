@@ -53,7 +53,9 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    path = os.path.join(_HERE, _LIBNAME)
+    # XY_ORACLE_LIB: load another build of these sources (the mutation tests
+    # compile deliberately broken copies of the oracle to check that the pins fail)
+    path = os.environ.get("XY_ORACLE_LIB") or os.path.join(_HERE, _LIBNAME)
     if not os.path.exists(path):
         build(force=True)
     lib = ctypes.CDLL(path)
