@@ -142,6 +142,30 @@ int xy_get_labels(xy_handle *h, int32_t rep, int64_t *out);
  * of ceil(N/32) uint32 each (synchronizes). */
 int xy_get_bonds(xy_handle *h, int32_t rep, uint32_t *bx, uint32_t *by);
 
+/* Device views of replica rep after its most recent sweep, for checks that
+ * must run where the data is (a lattice of 2^32 sites does not fit a host
+ * copy in FP64).  All pointers are device addresses inside the handle's
+ * memory, owned by the handle and valid until the next call that sweeps,
+ * sets state or frees it; callers only read through them.
+ *   cos_plane, sin_plane  N FP32 each, row-major (x fastest): the state
+ *   labels                N entries of label_bits/8 bytes: the union-find
+ *                         forest of the sweep; the cluster root of site i is
+ *                         labels[labels[i]], the smallest site of its cluster
+ *   bond_x, bond_y        link bit planes of the sweep, as in xy_get_bonds
+ * XY_ESTATE if the replica has not swept yet. */
+typedef struct {
+    const float *cos_plane;
+    const float *sin_plane;
+    const void *labels;
+    const uint32_t *bond_x;
+    const uint32_t *bond_y;
+    int64_t L;
+    int32_t label_bits;
+    int32_t reserved;
+    uint64_t sweep; /* sweeps completed */
+} xy_views;
+int xy_get_views(xy_handle *h, int32_t rep, xy_views *out);
+
 /* beta of replica rep: set (takes effect from the next sweep) / read. */
 int xy_set_beta(xy_handle *h, int32_t rep, double beta);
 int xy_get_beta(xy_handle *h, int32_t rep, double *beta);

@@ -49,6 +49,13 @@ def build(force: bool = True) -> str:
     return out
 
 
+def _stale(path: str) -> bool:
+    if not os.path.exists(path):
+        return True
+    t = os.path.getmtime(path)
+    return any(os.path.getmtime(os.path.join(_HERE, f)) > t for f in _SOURCES)
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -56,7 +63,7 @@ def _load():
     # XY_ORACLE_LIB: load another build of these sources (the mutation tests
     # compile deliberately broken copies of the oracle to check that the pins fail)
     path = os.environ.get("XY_ORACLE_LIB") or os.path.join(_HERE, _LIBNAME)
-    if not os.path.exists(path):
+    if not os.environ.get("XY_ORACLE_LIB") and _stale(path):
         build(force=True)
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
@@ -70,6 +77,7 @@ def _load():
         "orc_hot_start": (None, [i64, u64, u32, i32, dp, dp]),
         "orc_bonds": (None, [i64, dp, dp, dbl, dp, u64, u32, u64, u8p, u8p, i64p]),
         "orc_label": (i32, [i64, u8p, u8p, i64p]),
+        "orc_links": (None, [i64, i64, i64p, u8p, dp, dp, dp, dp, dbl, dp, u64, u32, u64, u8p, i64p]),
         "orc_coin": (i32, [u64, u32, u64, i64]),
         "orc_flip": (None, [i64, i64p, dp, dp, dp, u64, u32, u64, i32]),
         "orc_renorm": (None, [i64, dp, dp, i32]),
@@ -149,6 +157,23 @@ def bonds(L, c, s, beta, r, seed, rep, t):
                       _ptr(r, ctypes.c_double), seed, rep, t, _ptr(bx, ctypes.c_uint8),
                       _ptr(by, ctypes.c_uint8), ctypes.byref(ties))
     return bx, by, int(ties.value)
+
+
+def links(L, site, dirs, ci, si, cj, sj, beta, r, seed, rep, t):
+    """Decisions (uint8) of the links site[k] -> right (dirs[k] = 0) or down
+    (dirs[k] = 1), from the given end spins; and the near-tie count."""
+    site = np.ascontiguousarray(site, dtype=np.int64)
+    n = site.size
+    dirs = np.ascontiguousarray(dirs, dtype=np.uint8)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (ci, si, cj, sj)]
+    assert dirs.size == n and all(a.size == n for a in arrs)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.zeros(n, dtype=np.uint8)
+    ties = ctypes.c_int64(0)
+    _load().orc_links(L, n, _ptr(site, ctypes.c_int64), _ptr(dirs, ctypes.c_uint8),
+                      *[_ptr(a, ctypes.c_double) for a in arrs], beta, _ptr(r, ctypes.c_double),
+                      seed, rep, t, _ptr(out, ctypes.c_uint8), ctypes.byref(ties))
+    return out, int(ties.value)
 
 
 def label(L, bx, by) -> np.ndarray:

@@ -192,6 +192,24 @@ void orc_bonds(int64_t L, const double *c, const double *s, double beta, const d
     }
 }
 
+/* The same decision for n chosen links, given the spins at both ends:      */
+/* link k joins site[k] to its right (dir[k] == 0) or lower (dir[k] == 1)    */
+/* neighbour; (ci, si) and (cj, sj) are the two end spins.  Used to check a  */
+/* lattice too large for a host copy on a sample of its links.              */
+void orc_links(int64_t L, int64_t n, const int64_t *site, const uint8_t *dir, const double *ci,
+               const double *si, const double *cj, const double *sj, double beta, const double r[2],
+               uint64_t seed, uint32_t rep, uint64_t t, uint8_t *active, int64_t *ties)
+{
+    *ties = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t x = site[k] % L, y = site[k] / L;
+        uint32_t w[4];
+        draw(seed, (uint32_t)((y >> 1) * L + x), rep, (uint32_t)t, TAG_BOND, w);
+        uint32_t wk = w[2 * (int)(y & 1) + (dir[k] ? 1 : 0)];
+        active[k] = (uint8_t)bond_decision(proj(ci[k], si[k], r), proj(cj[k], sj[k], r), beta, wk, ties);
+    }
+}
+
 /* Connected components of the active-bond graph by breadth-first search.    */
 /* Sites are scanned in ascending index order and each new component is      */
 /* labelled by the site that opened it, i.e. by its minimum site index.      */

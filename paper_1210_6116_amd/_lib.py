@@ -45,6 +45,12 @@ class xy_pcc(ctypes.Structure):
                 ("halve_every", ctypes.c_int64), ("target", ctypes.c_double)]
 
 
+class xy_views(ctypes.Structure):
+    _fields_ = [("cos_plane", ctypes.c_void_p), ("sin_plane", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("bond_x", ctypes.c_void_p), ("bond_y", ctypes.c_void_p), ("L", ctypes.c_int64),
+                ("label_bits", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sweep", ctypes.c_uint64)]
+
+
 OBS_DTYPE = np.dtype([("sweep", np.uint64), ("beta", np.float64), ("E", np.float64), ("m2", np.float64),
                       ("ex", np.float64), ("sx", np.float64), ("ey", np.float64), ("sy", np.float64),
                       ("ups_x", np.float64), ("near_ties", np.uint64)])
@@ -67,6 +73,7 @@ _SIGS = {
     "xy_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "xy_get_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "xy_get_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_get_views": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(xy_views)]),
     "xy_set_beta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double]),
     "xy_get_beta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double)]),
     "xy_get_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_uint64), ctypes.c_void_p]),
@@ -164,6 +171,12 @@ def xy_get_labels(h, rep: int, out: np.ndarray):
 
 def xy_get_bonds(h, rep: int, bx: np.ndarray, by: np.ndarray):
     _check(load().xy_get_bonds(h, rep, _ptr(bx), _ptr(by)))
+
+
+def xy_get_views(h, rep: int) -> xy_views:
+    out = xy_views()
+    _check(load().xy_get_views(h, rep, ctypes.byref(out)))
+    return out
 
 
 def xy_set_beta(h, rep: int, beta: float):

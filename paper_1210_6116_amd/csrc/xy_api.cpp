@@ -615,6 +615,29 @@ int xy_get_bonds(xy_handle *h, int32_t rep, uint32_t *bx, uint32_t *by)
     return XY_OK;
 }
 
+int xy_get_views(xy_handle *h, int32_t rep, xy_views *out)
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    if (!out) return fail(XY_EINVAL, "output pointer is NULL");
+    xy::RepState s;
+    rc = read_state(h, rep, &s);
+    if (rc) return rc;
+    if (s.t == 0) return fail(XY_ESTATE, "replica %d has not swept yet", rep);
+    const xy::RepDesc &d = h->reps[rep];
+    const int par = (int)((s.t - 1) & 1);
+    *out = xy_views{};
+    out->cos_plane = d.c;
+    out->sin_plane = d.s;
+    out->labels = d.lab[par];
+    out->bond_x = d.bx[par];
+    out->bond_y = d.by[par];
+    out->L = d.L;
+    out->label_bits = h->plan.label_bits;
+    out->sweep = s.t;
+    return XY_OK;
+}
+
 int xy_set_beta(xy_handle *h, int32_t rep, double beta)
 {
     int rc = check_rep(h, rep);

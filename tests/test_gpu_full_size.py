@@ -1,0 +1,193 @@
+"""Checks at the full sizes of the timed workloads.
+
+L = 4096 (the plain-sweep throughput lattice): several sweeps in one call run
+the fused flip + next-links pass exactly as the throughput run does; the whole
+state, the labels, the links and every observable are compared with the oracle
+element by element.
+
+L = 65536 (N = 2^32 sites, 64-bit labels; the PCC throughput lattice): the
+oracle cannot hold it, so the sweep is checked
+  * on a seeded sample of links and sites that the oracle decides one by one:
+    link decisions from the pre-sweep spins (bit-exact) and reflections of the
+    sampled sites given their cluster roots (bit-exact);
+  * everywhere, on the device, by properties that hold at any size: every root
+    is a fixed point of the forest and no larger than its sites; the two ends
+    of every active link share a root; spins stay unit vectors; and the
+    observables equal an FP64 recomputation of the sums from the state.
+Whether two distinct components were wrongly united is not decided at this
+size (that needs a labelling of the whole lattice); the small-size parity
+tests decide it exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import xyworkloads as wl
+
+pytestmark = pytest.mark.gpu
+
+OBS_TOL = 1e-10
+NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x")
+
+
+def test_full_size_l4096_fused_sweeps():
+    import paper_1210_6116_amd as xy
+    L, beta, seed = 4096, 1.12, wl.SEED_L4096
+    print("L=4096 fused sweeps", flush=True)
+    lat = xy.Lattices(dict(L=L, beta=beta, seed=seed))
+    c0, s0 = wl.random_spins(L, 4097)
+    lat.set_state(c0, s0)
+    orc = oracle.Lattice(L=L, beta=beta, seed=seed, storage32=True, c=c0.astype(np.float64),
+                         s=s0.astype(np.float64))
+    tr_g = lat.sweep(3, trace=True)
+    tr_o, ties_o = orc.run(2)
+    obs_o, t_o, bx_o, by_o, lab_o = orc.sweep_detail()
+    cg, sg = lat.get_state()
+    assert np.array_equal(cg.astype(np.float64), orc.c) and np.array_equal(sg.astype(np.float64), orc.s)
+    bx_g, by_g = lat.bonds()
+    assert np.array_equal(bx_g, bx_o) and np.array_equal(by_g, by_o)
+    assert np.array_equal(lat.labels(), lab_o)
+    for k, name in enumerate(NAMES):
+        assert np.max(np.abs(tr_g[:2, 0][name] - tr_o[:, k])) <= OBS_TOL, name
+        assert abs(float(tr_g[2, 0][name]) - obs_o[k]) <= OBS_TOL, name
+    assert int(tr_g[2, 0]["near_ties"]) == t_o
+    lat.close()
+
+
+def _bits(words: torch.Tensor, lo: int, n: int) -> torch.Tensor:
+    """Bits lo .. lo+n-1 of a little-endian int32 word plane (lo, n multiples of 32)."""
+    w = words[lo // 32:(lo + n) // 32]
+    sh = torch.arange(32, device=w.device, dtype=torch.int32)
+    return ((w.unsqueeze(1) >> sh) & 1).reshape(-1).bool()
+
+
+def _roots(lab: torch.Tensor, idx: torch.Tensor) -> torch.Tensor:
+    return lab.index_select(0, lab.index_select(0, idx))
+
+
+def test_l65536_sampled_oracle_and_invariants():
+    import paper_1210_6116_amd as xy
+    L, beta, seed, rep = 65536, 1.12, wl.SEED_L65536, 0
+    N = L * L
+    print("L=65536 allocate", flush=True)
+    lat = xy.Lattices(dict(L=L, beta=beta, seed=seed, rep=rep))
+    assert lat.bytes < 100 * 2 ** 30
+    lat.sweep(1)  # sweep 0 from the hot start
+    torch.cuda.synchronize()
+    dev = lat.arena.device
+
+    # seeded sample: random sites plus tile-edge and wrap-around sites
+    rng = np.random.default_rng(0x65536)
+    xs = np.concatenate([rng.integers(0, L, 6000), np.full(500, L - 1), rng.integers(0, L // 64, 500) * 64 + 63,
+                         rng.integers(0, L, 1000)])
+    ys = np.concatenate([rng.integers(0, L, 6000), rng.integers(0, L, 500), rng.integers(0, L, 500),
+                         np.full(500, L - 1), rng.integers(0, L // 32, 500) * 32 + 31])
+    site = (ys.astype(np.int64) * L + xs).astype(np.int64)
+    right = ys.astype(np.int64) * L + (xs + 1) % L
+    down = ((ys + 1) % L).astype(np.int64) * L + xs
+    di = torch.from_numpy(site).to(dev)
+    dr = torch.from_numpy(right).to(dev)
+    dd = torch.from_numpy(down).to(dev)
+
+    v = lat.views()
+    assert v["label_bits"] == 64 and v["sweep"] == 1
+    c, s = v["cos"], v["sin"]
+    pre_ci, pre_si = c.index_select(0, di).double().cpu().numpy(), s.index_select(0, di).double().cpu().numpy()
+    pre_cr, pre_sr = c.index_select(0, dr).double().cpu().numpy(), s.index_select(0, dr).double().cpu().numpy()
+    pre_cd, pre_sd = c.index_select(0, dd).double().cpu().numpy(), s.index_select(0, dd).double().cpu().numpy()
+
+    print("L=65536 sweep 1", flush=True)
+    t = 1
+    r = oracle.direction(seed, rep, t)
+    assert np.array_equal(lat.sweep_count()[1], r)
+    tr = lat.sweep(1, trace=True)
+    torch.cuda.synchronize()
+    v = lat.views()
+    assert v["sweep"] == 2
+    lab, bxw, byw = v["labels"], v["bx"], v["by"]
+
+    # 1. sampled link decisions against the oracle, from the pre-sweep spins
+    def gather_bits(words, ix):
+        w = words.index_select(0, ix // 32)
+        return ((w >> (ix % 32).int()) & 1).cpu().numpy().astype(np.uint8)
+
+    gx, gy = gather_bits(bxw, di), gather_bits(byw, di)
+    n = site.size
+    ox, tx = oracle.links(L, site, np.zeros(n, np.uint8), pre_ci, pre_si, pre_cr, pre_sr, beta, r, seed, rep, t)
+    oy, ty = oracle.links(L, site, np.ones(n, np.uint8), pre_ci, pre_si, pre_cd, pre_sd, beta, r, seed, rep, t)
+    # a near tie (|u - p| < 1e-9) could legitimately differ; none is expected
+    # among 16000 links, and then every decision must agree
+    assert tx + ty == 0
+    assert np.array_equal(gx, ox), np.flatnonzero(gx != ox)[:10]
+    assert np.array_equal(gy, oy), np.flatnonzero(gy != oy)[:10]
+    assert gx.sum() > 0 and gy.sum() > 0
+
+    # 2. sampled reflections: the oracle flips the sampled sites given their roots
+    roots_i = _roots(lab, di)
+    side = int(np.sqrt(n))
+    m = side * side
+    ri = roots_i.cpu().numpy()
+    exp_c, exp_s = oracle.flip(side, ri[:m], pre_ci[:m], pre_si[:m], r, seed, rep, t)
+    post_c = c.index_select(0, di).double().cpu().numpy()
+    post_s = s.index_select(0, di).double().cpu().numpy()
+    assert np.array_equal(post_c[:m], exp_c) and np.array_equal(post_s[:m], exp_s)
+    flipped = post_c[:m] != pre_ci[:m]
+    assert 0.2 < flipped.mean() < 0.8
+
+    # 3. label forest properties and link consistency, whole lattice, by row blocks
+    print("L=65536 invariants", flush=True)
+    rows = 1024
+    ar_cache = None
+    n_active = 0
+    for y0 in range(0, L, rows):
+        lo, cnt = y0 * L, rows * L
+        if ar_cache is None:
+            ar_cache = torch.arange(cnt, device=dev, dtype=torch.int64)
+        idx = ar_cache + lo
+        first = lab[lo:lo + cnt].long()
+        assert bool((first <= idx).all()), y0
+        root = lab.index_select(0, first).long()
+        assert bool((lab.index_select(0, root).long() == root).all()), y0
+        assert bool((root <= idx).all()), y0
+        rr = root.view(rows, L)
+        ax = _bits(bxw, lo, cnt).view(rows, L)
+        assert bool((rr[ax] == rr.roll(-1, dims=1)[ax]).all()), ("x links", y0)
+        y1 = (y0 + rows) % L
+        below_first = lab[y1 * L:(y1 + 1) * L].long()
+        below = lab.index_select(0, below_first).long()
+        down_roots = torch.cat([rr[1:], below.view(1, L)], dim=0)
+        ay = _bits(byw, lo, cnt).view(rows, L)
+        assert bool((rr[ay] == down_roots[ay]).all()), ("y links", y0)
+        n_active += int(ax.sum()) + int(ay.sum())
+        del first, root, rr, ax, ay, below, below_first, down_roots, idx
+    assert 0 < n_active < 2 * N
+
+    # 4. unit spins and observables from an FP64 recomputation of the sums
+    print("L=65536 observables", flush=True)
+    sums = np.zeros(6)
+    norm_dev = 0.0
+    for y0 in range(0, L, rows):
+        lo, cnt = y0 * L, rows * L
+        cb = c[lo:lo + cnt].double().view(rows, L)
+        sb = s[lo:lo + cnt].double().view(rows, L)
+        y1 = (y0 + rows) % L
+        cd = torch.cat([cb[1:], c[y1 * L:(y1 + 1) * L].double().view(1, L)], 0)
+        sd = torch.cat([sb[1:], s[y1 * L:(y1 + 1) * L].double().view(1, L)], 0)
+        cr, sr = cb.roll(-1, dims=1), sb.roll(-1, dims=1)
+        sums += np.array([float((cb * cr + sb * sr).sum()), float((sb * cr - cb * sr).sum()),
+                          float((cb * cd + sb * sd).sum()), float((sb * cd - cb * sd).sum()),
+                          float(cb.sum()), float(sb.sum())])
+        norm_dev = max(norm_dev, float((cb * cb + sb * sb - 1.0).abs().max()))
+    assert norm_dev < 1e-6
+    scx, ssx, scy, ssy, sc, ss = sums
+    ref = {"E": -(scx + scy) / N, "m2": (sc * sc + ss * ss) / (N * float(N)), "ex": scx / N, "sx": ssx / N,
+           "ey": scy / N, "sy": ssy / N}
+    ref["ups_x"] = ref["ex"] - beta * N * ref["sx"] ** 2
+    g = tr[0, 0]
+    for name in NAMES:
+        assert abs(float(g[name]) - ref[name]) <= OBS_TOL, (name, float(g[name]), ref[name])
+    assert -2.0 < float(g["E"]) < 0.0
+    lat.close()
+    del lat, v, lab, bxw, byw, c, s
+    torch.cuda.empty_cache()

@@ -56,6 +56,32 @@ def test_beta_infinite_clusters_are_same_sign_domains():
     assert bx0.sum() == 0 and by0.sum() == 0
 
 
+def test_sampled_links_match_whole_lattice_decisions():
+    # the one-link form (used on samples of lattices too large to copy) takes
+    # every decision as the whole-lattice pass does, at every site and both
+    # directions, including the wrap-around links of the last row and column
+    L, beta, seed, rep, t = 16, 1.12, 0x5A11, 3, 7
+    c, s = wl.random_spins(L, seed=17)
+    c = c.astype(np.float64)
+    s = s.astype(np.float64)
+    r = oracle.direction(seed, rep, t)
+    bx, by, ties = oracle.bonds(L, c, s, beta, r, seed, rep, t)
+    idx = np.arange(L * L)
+    right = (idx // L) * L + (idx % L + 1) % L
+    down = ((idx // L + 1) % L) * L + idx % L
+    site = np.concatenate([idx, idx])
+    dirs = np.concatenate([np.zeros(L * L), np.ones(L * L)]).astype(np.uint8)
+    nb = np.concatenate([right, down])
+    act, ties1 = oracle.links(L, site, dirs, c[site], s[site], c[nb], s[nb], beta, r, seed, rep, t)
+    assert np.array_equal(act[:L * L], bx) and np.array_equal(act[L * L:], by)
+    assert ties1 == ties
+    # and in the beta -> infinity limit a sampled link is active iff the end
+    # spins project on r with the same sign
+    a = c * r[0] + s * r[1]
+    act_inf, _ = oracle.links(L, site, dirs, c[site], s[site], c[nb], s[nb], 1e9, r, seed, rep, t)
+    assert np.array_equal(act_inf.astype(bool), (a[site] > 0) == (a[nb] > 0))
+
+
 def test_bond_fraction_grows_with_beta():
     L = 32
     c, s = wl.random_spins(L, seed=5)
