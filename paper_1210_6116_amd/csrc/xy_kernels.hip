@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "xy_device.hpp"
 #include "xy_launch.hpp"
 
@@ -258,12 +260,13 @@ __global__ __launch_bounds__(kThreads) void k_init_spins(const RepDesc *__restri
                                                           int32_t start)
 {
     const RepDesc &R = reps[r];
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= R.N) return;
-    double x = 1.0, y = 0.0;
-    if (start == XY_START_HOT) disk_point(R.seed, R.rep, TAG_INIT, (uint32_t)i, 0u, false, &x, &y);
-    R.c[i] = (float)x;
-    R.s[i] = (float)y;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < R.N; i += stride) {
+        double x = 1.0, y = 0.0;
+        if (start == XY_START_HOT) disk_point(R.seed, R.rep, TAG_INIT, (uint32_t)i, 0u, false, &x, &y);
+        R.c[i] = (float)x;
+        R.s[i] = (float)y;
+    }
 }
 
 // Edge copies (first column, then first row of every tile) of the current
@@ -833,18 +836,19 @@ template <typename LT>
 __global__ __launch_bounds__(kThreads) void k_flatten(const LT *__restrict__ lab, int64_t N, void *out,
                                                        int32_t out_bits)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= N) return;
-    LT x = (LT)i;
-    while (true) {
-        const LT p = lab[x];
-        if (p == x) break;
-        x = p;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < N; i += stride) {
+        LT x = (LT)i;
+        while (true) {
+            const LT p = lab[x];
+            if (p == x) break;
+            x = p;
+        }
+        if (out_bits == 64)
+            ((uint64_t *)out)[i] = (uint64_t)x;
+        else
+            ((uint32_t *)out)[i] = (uint32_t)x;
     }
-    if (out_bits == 64)
-        ((uint64_t *)out)[i] = (uint64_t)x;
-    else
-        ((uint32_t *)out)[i] = (uint32_t)x;
 }
 
 // ====================================================== host-side launchers
@@ -854,9 +858,13 @@ size_t lds_bytes_tile(int TH, int label_bits)
     return (size_t)(TH + 1) * 65 * sizeof(float2) + 2 * 64 * sizeof(uint64_t) + (size_t)64 * TH * sizeof(uint32_t);
 }
 
+// Element-wise kernels over N sites loop with a grid stride: a dispatch holds
+// fewer than 2^32 work-items, and N reaches 2^32.
+constexpr int64_t kMaxStrideBlocks = 1 << 20;
+
 hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s)
 {
-    const int64_t blocks = (N + kThreads - 1) / kThreads;
+    const int64_t blocks = std::min<int64_t>((N + kThreads - 1) / kThreads, kMaxStrideBlocks);
     hipLaunchKernelGGL(k_init_spins, dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, start);
     return hipGetLastError();
 }
@@ -968,7 +976,7 @@ hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &
 hipError_t launch_flatten(const void *d_lab, int32_t label_bits, int64_t N, void *d_out, int32_t out_bits,
                           hipStream_t s)
 {
-    const int64_t blocks = (N + kThreads - 1) / kThreads;
+    const int64_t blocks = std::min<int64_t>((N + kThreads - 1) / kThreads, kMaxStrideBlocks);
     if (label_bits == 64)
         hipLaunchKernelGGL((k_flatten<unsigned long long>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
                            (const unsigned long long *)d_lab, N, d_out, out_bits);

@@ -49,7 +49,8 @@ def _run_group(requests, budget=2 * 10 ** 9, max_slots=8, rounds=7):
     while len(out) < len(requests):
         for k, (adm, L, seed, sweeps) in enumerate(requests):
             if adm == r and k not in slot_of.values():
-                s = g.add(L, seed, 1.0, sweeps, replica=k)
+                # a request's stream is (seed, replica 0) whatever its position in the mix
+                s = g.add(L, seed, 1.0, sweeps, replica=0)
                 assert s is not None
                 slot_of[s] = k
         g.round(rounds)
