@@ -32,23 +32,32 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1210_6116_amd", "csrc", "xy_kernels.hip"
 COUNTERS = os.path.join(ROOT, "profiles", "counters_L4096.json")
 
 
-def alg_bytes_per_site(kernel: str, label_bytes: int) -> float:
-    """Algorithmic HBM bytes per site of one launch of each kernel.
+def alg_bytes_per_site(kernel: str, tile_rows: int = 32) -> float:
+    """Algorithmic HBM bytes per site of one launch of each kernel (64-column
+    tiles of tile_rows rows; labels are 16-bit and tile-local).
 
-    bonds_ccl: read both spin planes (8) + write the label (4 or 8) + the two
-               link bit planes (0.25) and the coin bits (0.125)
-    flip:      read the label (4 or 8), read and write both spin planes (16)
+    bonds_ccl: read both spin planes (8) + write the label (2) + the two link
+               bit planes (0.25) + the tile's edge slots and edge-link masks
+               ((2 (64 + rows) + 16) / (64 rows))
+    flip:      read the label (2), read and write both spin planes (16), write
+               the tile's edge copies and read the neighbours' ((64 + rows) 16
+               / (64 rows))
     fused:     flip of sweep t plus links / labels of sweep t+1 from the same
-               spins: read label, read + write spins, write label, bits
-               (the 24 B/site pass with 32-bit labels)
-    merge, finalize: only tile-edge links / per-tile sums: not counted
+               spins: the flip's bytes + the label, planes and edge records of
+               sweep t+1
+    merge, finalize: only tile-edge records / per-tile sums: not counted
     """
+    sites = 64.0 * tile_rows
+    edge_rec = (2.0 * (64 + tile_rows) + 16.0) / sites
+    edge_copies = (64 + tile_rows) * 16.0 / sites
+    bonds = 8.0 + 2.0 + 0.25 + edge_rec
+    flip = 2.0 + 16.0 + edge_copies
     if kernel == "bonds_ccl":
-        return 8.0 + label_bytes + 0.375
+        return bonds
     if kernel == "flip":
-        return label_bytes + 16.0
+        return flip
     if kernel == "fused":
-        return 2.0 * label_bytes + 16.0 + 0.375
+        return flip + 2.0 + 0.25 + edge_rec
     return 0.0
 
 
@@ -122,7 +131,7 @@ def bench_l65536(sweeps: int):
     del lat
     torch.cuda.empty_cache()
     per = list(per)
-    return {"workload": "PCC run, L=65536, uint64 labels, beta0=1.0, window 1, dbeta 0.004 halved every "
+    return {"workload": "PCC run, L=65536, uint64 canonical labels, beta0=1.0, window 1, dbeta 0.004 halved every "
                         "250 steps (floor 0.0005); %d timed sweeps after 2" % sweeps,
             "value": sweeps * L * L / dt, "unit": "spin updates/s", "ms_per_sweep": dt / sweeps * 1e3,
             "sweep_ms_p50": percentile(per, 50), "sweep_ms_p99": percentile(per, 99),
@@ -232,7 +241,8 @@ def main():
     print("bench: L=%d beta=%g warmup=%d steps=%d" % (L, beta, args.warmup, args.steps), file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
     lat = xy.Lattices(dict(L=L, beta=beta, seed=seed, tile_rows=args.tile_rows), stream=stream)
-    label_bytes = 8 if N >= 2 ** 32 else 4
+    label_bits = 64 if N >= 2 ** 32 else 32
+    rows = args.tile_rows or 32
 
     lat.sweep(args.warmup)
     torch.cuda.synchronize()
@@ -259,7 +269,7 @@ def main():
         for k, name in enumerate(xy._lib.KERNEL_NAMES):
             if launches[k] and name != "sweep":
                 avg = ms[k] / launches[k]
-                ab = alg_bytes_per_site(name, label_bytes) * N
+                ab = alg_bytes_per_site(name, rows) * N
                 kernels[name] = {"launches": int(launches[k]), "avg_ms": avg, "alg_bytes": ab,
                                  "alg_GBps": (ab / (avg * 1e-3) / 1e9) if ab else None}
         dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
@@ -286,8 +296,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 state, f64 reflection and sums",
         "data": "synthetic (seeded Philox hot start)",
-        "config": {"workload": "plain SW sweep, 2D XY periodic L=%d, beta=%g, uint%d labels, "
-                               "%d thermalisation + %d timed sweeps" % (L, beta, 8 * label_bytes,
+        "config": {"workload": "plain SW sweep, 2D XY periodic L=%d, beta=%g, uint%d canonical labels "
+                               "(16-bit tile-local labels in the sweep), %d thermalisation + %d timed "
+                               "sweeps" % (L, beta, label_bits,
                                                                          args.warmup, args.steps),
                    "L": L, "beta": beta, "seed": seed, "parallelism": "single GPU"},
         "roofline": roofline,

@@ -60,7 +60,10 @@ typedef struct {
     double beta;        /* inverse temperature (J = 1), 0 <= beta <= 1e4 */
     uint64_t seed;      /* 64-bit Philox4x32-10 key */
     uint32_t replica;   /* stream id (Philox counter word 1) */
-    int32_t label_bits; /* 32, 64, or 0 = automatic (64 iff L*L >= 2^32) */
+    int32_t label_bits; /* width of the canonical labels handed out (xy_flatten_labels):
+                           32, 64, or 0 = automatic (64 iff L*L >= 2^32).  Labels are
+                           kept per tile in 16 bits, with a 64-bit forest of the
+                           components that cross tile edges, whatever this is. */
     int32_t start;      /* XY_START_HOT or XY_START_COLD */
     int32_t tile_rows;  /* rows of a labelling tile: 16, 32, 64, or 0 = automatic */
 } xy_params;
@@ -148,15 +151,13 @@ int xy_get_bonds(xy_handle *h, int32_t rep, uint32_t *bx, uint32_t *by);
  * memory, owned by the handle and valid until the next call that sweeps,
  * sets state or frees it; callers only read through them.
  *   cos_plane, sin_plane  N FP32 each, row-major (x fastest): the state
- *   labels                N entries of label_bits/8 bytes: the union-find
- *                         forest of the sweep; the cluster root of site i is
- *                         labels[labels[i]], the smallest site of its cluster
  *   bond_x, bond_y        link bit planes of the sweep, as in xy_get_bonds
+ *   label_bits            width of the canonical labels (32 or 64) that
+ *                         xy_flatten_labels writes by default
  * XY_ESTATE if the replica has not swept yet. */
 typedef struct {
     const float *cos_plane;
     const float *sin_plane;
-    const void *labels;
     const uint32_t *bond_x;
     const uint32_t *bond_y;
     int64_t L;
@@ -165,6 +166,13 @@ typedef struct {
     uint64_t sweep; /* sweeps completed */
 } xy_views;
 int xy_get_views(xy_handle *h, int32_t rep, xy_views *out);
+
+/* Canonical cluster labels of the most recent sweep of replica rep (the
+ * flatten of the two-level labelling: every site gets the smallest site index
+ * of its cluster), written to d_out, caller-owned device memory of N entries
+ * of out_bits/8 bytes (out_bits 32 or 64; 32 only if N <= 2^32).  Runs on the
+ * handle's stream and synchronizes it. */
+int xy_flatten_labels(xy_handle *h, int32_t rep, void *d_out, int32_t out_bits);
 
 /* beta of replica rep: set (takes effect from the next sweep) / read. */
 int xy_set_beta(xy_handle *h, int32_t rep, double beta);

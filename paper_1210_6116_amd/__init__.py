@@ -109,15 +109,13 @@ class Lattices:
         return unpack_bits(bx, self.N[rep]), unpack_bits(by, self.N[rep])
 
     def views(self, rep: int = 0) -> dict:
-        """Device tensors (no copies) of the state, label forest and link planes
-        after the latest sweep: cos, sin (float32, N), labels (int32 or int64, N;
-        the root of site i is labels[labels[i]]; int32 values are read unsigned
-        by masking), bx, by (int32 words).  Valid until the next call on the handle."""
+        """Device tensors (no copies) of the state and link planes after the
+        latest sweep: cos, sin (float32, N), bx, by (int32 words).  Valid until
+        the next call on the handle."""
         v = _lib.xy_get_views(self.h, rep)
         base = self.arena.data_ptr()
         N = self.N[rep]
         words = max(1, (N + 31) // 32)
-        lab_dt, lab_sz = (torch.int64, 8) if v.label_bits == 64 else (torch.int32, 4)
 
         def sub(ptr, nbytes, dtype):
             off = ptr - base
@@ -125,9 +123,15 @@ class Lattices:
             return self.arena[off:off + nbytes].view(dtype)
 
         return {"cos": sub(v.cos_plane, 4 * N, torch.float32), "sin": sub(v.sin_plane, 4 * N, torch.float32),
-                "labels": sub(v.labels, lab_sz * N, lab_dt), "bx": sub(v.bond_x, 4 * words, torch.int32),
-                "by": sub(v.bond_y, 4 * words, torch.int32), "label_bits": v.label_bits, "L": v.L,
-                "sweep": v.sweep}
+                "bx": sub(v.bond_x, 4 * words, torch.int32), "by": sub(v.bond_y, 4 * words, torch.int32),
+                "label_bits": v.label_bits, "L": v.L, "sweep": v.sweep}
+
+    def labels_device(self, rep: int = 0, bits: int = 64) -> torch.Tensor:
+        """Canonical labels of the latest sweep in a new device tensor (int64,
+        or int32 holding the unsigned 32-bit labels)."""
+        out = torch.empty(self.N[rep], dtype=torch.int64 if bits == 64 else torch.int32, device=self.device)
+        _lib.xy_flatten_labels(self.h, rep, out.data_ptr(), bits)
+        return out
 
     def beta(self, rep: int = 0) -> float:
         return _lib.xy_get_beta(self.h, rep)

@@ -46,7 +46,7 @@ class xy_pcc(ctypes.Structure):
 
 
 class xy_views(ctypes.Structure):
-    _fields_ = [("cos_plane", ctypes.c_void_p), ("sin_plane", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+    _fields_ = [("cos_plane", ctypes.c_void_p), ("sin_plane", ctypes.c_void_p),
                 ("bond_x", ctypes.c_void_p), ("bond_y", ctypes.c_void_p), ("L", ctypes.c_int64),
                 ("label_bits", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sweep", ctypes.c_uint64)]
 
@@ -73,6 +73,7 @@ _SIGS = {
     "xy_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "xy_get_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "xy_get_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_flatten_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32]),
     "xy_get_views": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(xy_views)]),
     "xy_set_beta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double]),
     "xy_get_beta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double)]),
@@ -171,6 +172,10 @@ def xy_get_labels(h, rep: int, out: np.ndarray):
 
 def xy_get_bonds(h, rep: int, bx: np.ndarray, by: np.ndarray):
     _check(load().xy_get_bonds(h, rep, _ptr(bx), _ptr(by)))
+
+
+def xy_flatten_labels(h, rep: int, d_out: int, out_bits: int):
+    _check(load().xy_flatten_labels(h, rep, d_out, out_bits))
 
 
 def xy_get_views(h, rep: int) -> xy_views:

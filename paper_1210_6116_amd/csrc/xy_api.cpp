@@ -83,12 +83,10 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
     }
     if (want32 && (need64 || want64)) return fail(XY_EINVAL, "replicas disagree on the label width");
     P.label_bits = (need64 || want64) ? 64 : 32;
-    P.pingpong = maxN < (int64_t(1) << 30);
     // 64-bit site indices are needed above 2^30 sites; XY_WIDE_INDEX=1 selects
     // them for any size (the same kernels with wider index arithmetic; tests)
     const char *wide = std::getenv("XY_WIDE_INDEX");
     P.big_index = maxN > (int64_t(1) << 30) || (wide && wide[0] == '1');
-    const int lb = P.label_bits / 8;
     size_t off = 0;
     P.res.resize(n);
     P.lay.resize(n);
@@ -97,12 +95,12 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         Resolved &r = P.res[k];
         r.L = p[k].L;
         r.N = r.L * r.L;
-        int rows = p[k].tile_rows ? p[k].tile_rows : 32;
-        if (P.label_bits == 64) rows = std::min(rows, 32);
+        const int rows = p[k].tile_rows ? p[k].tile_rows : 32;
         r.TW = (int32_t)std::min<int64_t>(r.L, 64);
         r.TH = (int32_t)std::min<int64_t>(r.L, rows);
         r.ntx = (int32_t)(r.L / r.TW);
         r.nty = (int32_t)(r.L / r.TH);
+        r.nb = 2 * (r.TW + r.TH);
         r.ntiles = (int64_t)r.ntx * r.nty;
         P.max_th = std::max(P.max_th, r.TH);
         P.uniform_tw = (P.uniform_tw < 0 || P.uniform_tw == r.TW) ? r.TW : 0;
@@ -110,32 +108,31 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         P.total_tiles += r.ntiles;
         RepLayout &l = P.lay[k];
         const size_t words = (size_t)std::max<int64_t>(1, (r.N + 31) / 32);
+        const size_t nodes = (size_t)r.ntiles * r.nb;
         l.c = off;
         off = align_up(off + (size_t)r.N * 4);
         l.s = off;
         off = align_up(off + (size_t)r.N * 4);
+        // everything a sweep produces is double-buffered: the fused pass reads
+        // slot t&1 (flip of sweep t) while it writes slot (t+1)&1
         for (int q = 0; q < 2; ++q) {
-            // edge copies are always double-buffered (the flip reads one slot
-            // and writes the other); labels and link planes only with pingpong
             l.edge[q] = off;
             off = align_up(off + (size_t)r.ntiles * (r.TH + r.TW) * sizeof(float2));
-            if (q == 1 && !P.pingpong) {
-                l.lab[1] = l.lab[0];
-                l.bx[1] = l.bx[0];
-                l.by[1] = l.by[0];
-                continue;
-            }
             l.lab[q] = off;
-            off = align_up(off + (size_t)r.N * lb);
+            off = align_up(off + (size_t)r.N * sizeof(uint16_t));
             l.bx[q] = off;
             off = align_up(off + words * 4);
             l.by[q] = off;
             off = align_up(off + words * 4);
+            l.bslot[q] = off;
+            off = align_up(off + nodes);
+            l.node[q] = off;
+            off = align_up(off + nodes * sizeof(unsigned long long));
+            l.cross[q] = off;
+            off = align_up(off + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
         }
-        for (int q = 0; q < 2; ++q) {
-            l.coins[q] = off;
-            off = align_up(off + std::max<size_t>(words, 4) * 4);
-        }
+        l.scoin = off;
+        off = align_up(off + (size_t)r.ntiles * 4 * sizeof(unsigned long long));
         l.partials = off;
         off = align_up(off + (size_t)r.ntiles * xy::kNumSums * sizeof(double));
         l.end = off;
@@ -161,12 +158,15 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
     d.c = reinterpret_cast<float *>(A + l.c);
     d.s = reinterpret_cast<float *>(A + l.s);
     for (int q = 0; q < 2; ++q) {
-        d.lab[q] = A + l.lab[q];
+        d.lab[q] = reinterpret_cast<uint16_t *>(A + l.lab[q]);
         d.bx[q] = reinterpret_cast<uint32_t *>(A + l.bx[q]);
         d.by[q] = reinterpret_cast<uint32_t *>(A + l.by[q]);
+        d.bslot[q] = reinterpret_cast<uint8_t *>(A + l.bslot[q]);
+        d.node[q] = reinterpret_cast<unsigned long long *>(A + l.node[q]);
+        d.cross[q] = reinterpret_cast<unsigned long long *>(A + l.cross[q]);
         d.edge[q] = reinterpret_cast<float2 *>(A + l.edge[q]);
-        d.coins[q] = reinterpret_cast<uint32_t *>(A + l.coins[q]);
     }
+    d.scoin = reinterpret_cast<unsigned long long *>(A + l.scoin);
     d.partials = reinterpret_cast<double *>(A + l.partials);
     d.st = st;
     d.L = r.L;
@@ -181,6 +181,7 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
     d.log2TW = ilog2(r.TW);
     d.ntx = r.ntx;
     d.nty = r.nty;
+    d.nb = r.nb;
     d.idx = idx;
 }
 
@@ -297,7 +298,7 @@ int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, bool *re
         HIPCHECK(h, hipEventRecord(sweep_begin, h->stream));
     }
     auto timer = [&](int kind, auto launch) { return timed(h, kind, launch); };
-    HIPCHECK(h, enqueue_sweep_lc(lc, h->d_reps, h->plan.n, h->plan.pingpong, fa, fuse_next, ready, h->stream, timer));
+    HIPCHECK(h, enqueue_sweep_lc(lc, h->d_reps, h->plan.n, fa, fuse_next, ready, h->stream, timer));
     if (h->timing) {
         xy_handle::Ev ev;
         ev.kind = XY_K_SWEEP;
@@ -579,24 +580,40 @@ int xy_set_state(xy_handle *h, int32_t rep, const float *cos_in, const float *si
     return XY_OK;
 }
 
+int xy_flatten_labels(xy_handle *h, int32_t rep, void *d_out, int32_t out_bits)
+{
+    int rc = check_rep(h, rep);
+    if (rc) return rc;
+    if (!d_out) return fail(XY_EINVAL, "output pointer is NULL");
+    if (out_bits != 32 && out_bits != 64) return fail(XY_EINVAL, "out_bits=%d is not 32 or 64", out_bits);
+    const xy::RepDesc &d = h->reps[rep];
+    if (out_bits == 32 && d.N > (int64_t(1) << 32))
+        return fail(XY_EINVAL, "labels of %lld sites need 64 bits", (long long)d.N);
+    xy::RepState s;
+    rc = read_state(h, rep, &s);
+    if (rc) return rc;
+    if (s.t == 0) return fail(XY_ESTATE, "replica %d has not swept yet", rep);
+    HIPCHECK(h, xy::launch_flatten(h->d_reps, rep, (int32_t)((s.t - 1) & 1), d.N, h->plan.big_index, d_out,
+                                   out_bits, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return XY_OK;
+}
+
 int xy_get_labels(xy_handle *h, int32_t rep, int64_t *out)
 {
     int rc = check_rep(h, rep);
     if (rc) return rc;
     if (!out) return fail(XY_EINVAL, "output pointer is NULL");
-    xy::RepState s;
-    rc = read_state(h, rep, &s);
-    if (rc) return rc;
-    if (s.t == 0) return fail(XY_ESTATE, "replica %d has not swept yet", rep);
     const xy::RepDesc &d = h->reps[rep];
     void *tmp = nullptr;
     HIPCHECK(h, hipMalloc(&tmp, d.N * sizeof(int64_t)));
-    hipError_t e = xy::launch_flatten(d.lab[(s.t - 1) & 1], h->plan.label_bits, d.N, tmp, 64, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess) e = hipMemcpy(out, tmp, d.N * sizeof(int64_t), hipMemcpyDeviceToHost);
+    rc = xy_flatten_labels(h, rep, tmp, 64);
+    if (rc == XY_OK) {
+        const hipError_t e = hipMemcpy(out, tmp, d.N * sizeof(int64_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = hip_fail(h, e, "label copy");
+    }
     (void)hipFree(tmp);
-    if (e != hipSuccess) return hip_fail(h, e, "label flatten");
-    return XY_OK;
+    return rc;
 }
 
 int xy_get_bonds(xy_handle *h, int32_t rep, uint32_t *bx, uint32_t *by)
@@ -629,7 +646,6 @@ int xy_get_views(xy_handle *h, int32_t rep, xy_views *out)
     *out = xy_views{};
     out->cos_plane = d.c;
     out->sin_plane = d.s;
-    out->labels = d.lab[par];
     out->bond_x = d.bx[par];
     out->bond_y = d.by[par];
     out->L = d.L;
@@ -690,11 +706,25 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     if (rc) return rc;
     const Resolved &r = P.res[0];
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // scratch: state + descriptor, then the tile-local labels and the forest
+    const size_t nodes = (size_t)r.ntiles * r.nb;
+    const size_t off_lab = 1024, off_bslot = align_up(off_lab + (size_t)r.N * sizeof(uint16_t));
+    const size_t off_node = align_up(off_bslot + nodes);
+    const size_t off_cross = align_up(off_node + nodes * sizeof(unsigned long long));
+    const size_t total = align_up(off_cross + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
+    char *mem = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&mem), total);
+    if (e != hipSuccess) return fail(XY_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
     xy::RepDesc d;
     std::memset(&d, 0, sizeof d);
-    d.lab[0] = d.lab[1] = d_labels;
-    d.bx[0] = d.bx[1] = const_cast<uint32_t *>(d_bx);
-    d.by[0] = d.by[1] = const_cast<uint32_t *>(d_by);
+    for (int q = 0; q < 2; ++q) {
+        d.lab[q] = reinterpret_cast<uint16_t *>(mem + off_lab);
+        d.bslot[q] = reinterpret_cast<uint8_t *>(mem + off_bslot);
+        d.node[q] = reinterpret_cast<unsigned long long *>(mem + off_node);
+        d.cross[q] = reinterpret_cast<unsigned long long *>(mem + off_cross);
+        d.bx[q] = const_cast<uint32_t *>(d_bx);
+        d.by[q] = const_cast<uint32_t *>(d_by);
+    }
     d.L = r.L;
     d.N = r.N;
     d.ntiles = r.ntiles;
@@ -704,13 +734,12 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     d.log2TW = ilog2(r.TW);
     d.ntx = r.ntx;
     d.nty = r.nty;
+    d.nb = r.nb;
     xy::RepState st;
     std::memset(&st, 0, sizeof st);
-    char *mem = nullptr;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&mem), 1024 + sizeof d + sizeof st);
-    if (e != hipSuccess) return fail(XY_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
     xy::RepState *d_st = reinterpret_cast<xy::RepState *>(mem);
     xy::RepDesc *d_rep = reinterpret_cast<xy::RepDesc *>(mem + 512);
+    static_assert(sizeof(xy::RepState) <= 512 && sizeof(xy::RepDesc) <= 512, "scratch header too small");
     d.st = d_st;
     e = hipMemcpy(d_st, &st, sizeof st, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_rep, &d, sizeof d, hipMemcpyHostToDevice);
@@ -727,7 +756,7 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     lc.gtile_end = r.ntiles;
     if (e == hipSuccess) e = xy::launch_tile(lc, xy::TILE_PLANES, s);
     if (e == hipSuccess) e = xy::launch_merge(lc, false, s);
-    if (e == hipSuccess) e = xy::launch_flatten(d_labels, label_bits, r.N, d_labels, label_bits, s);
+    if (e == hipSuccess) e = xy::launch_flatten(d_rep, 0, 0, r.N, P.big_index, d_labels, label_bits, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(mem);
     if (e != hipSuccess) return fail(XY_EDEVICE, "labelling failed: %s", hipGetErrorString(e));

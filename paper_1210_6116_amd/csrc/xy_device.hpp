@@ -19,6 +19,8 @@ namespace xy {
 //   BOND (pair = (y>>1)*L + x, rep, t, 1): words 0,1 = x-link, y-link of site
 //        (x, 2*(y>>1)); words 2,3 the same for site (x, 2*(y>>1)+1)
 //   FLIP (root>>7, rep, t, 2): coin of cluster root r = bit (r&31) of word (r>>5)&3
+//        (drawn where needed: per tile row for the tile's own roots, per slot
+//        for roots found through the boundary forest)
 //   DIR  (k, rep, t, 3), INIT (site, rep, k, 4): k-th attempt of a rejection
 //        draw of a point in the unit disk
 // ---------------------------------------------------------------------------
@@ -74,11 +76,30 @@ struct RepState {
     xy_obs last;             // observables after the latest sweep
 };
 
+// Labels of sweep t (slot t&1 of every double buffer below):
+//   lab[i]   16 bits per site, tile-local: the tile-local index y*TW + x of the
+//            smallest site of i's component inside its tile, or kBoundary | s
+//            when that component touches the tile's edge, s being its slot
+//   bslot    per tile NB = 2*(TW+TH) bytes: for every edge position p (top row,
+//            bottom row, left column, right column) the slot of its component,
+//            which is the smallest edge position of that component
+//   node     per tile NB packed words, one per used slot: (key << 32) | parent,
+//            key = global index of the smallest site of the parent's component;
+//            a root's parent is itself.  Node id = tile * NB + slot.
+//   cross    per tile two words: active links over the right edge (bit y) and
+//            over the bottom edge (bit x)
+//   scoin    per tile four words (one buffer): bit s = flip coin of the cluster
+//            of used slot s, drawn between the merge and the flip
+constexpr uint32_t kBoundary = 0x8000u;
+
 struct RepDesc {
     float *c, *s;            // spin planes, N floats each
-    void *lab[2];            // label forest of sweep t in slot t&1 (uint32 or uint64, N)
-    uint32_t *bx[2], *by[2]; // active-link bit planes of sweep t in slot t&1
-    uint32_t *coins[2];      // flip coins of sweep t in slot t&1, one bit per site
+    uint16_t *lab[2];        // tile-local labels
+    uint32_t *bx[2], *by[2]; // active-link bit planes
+    uint8_t *bslot[2];       // edge positions -> slot
+    unsigned long long *node[2];  // boundary-component forest
+    unsigned long long *cross[2]; // links over the right / bottom tile edges
+    unsigned long long *scoin;    // per tile 4 words: flip coin of every used edge slot
     float2 *edge[2];         // spins before sweep t in slot t&1: per tile, its first column (TH) then first row (TW)
     double *partials;        // kNumSums planes of per-tile sums: partials[k * ntiles + tile]
     RepState *st;
@@ -87,6 +108,7 @@ struct RepDesc {
     uint64_t seed;
     uint32_t rep;
     int32_t log2L, TW, TH, log2TW, ntx, nty;
+    int32_t nb;              // edge positions (and slots) per tile, 2 * (TW + TH)
     int32_t idx;             // position of the replica in its handle
 };
 
@@ -109,6 +131,16 @@ struct Tile {
         const IT y = i >> log2L, x = i & (L - 1);
         return (int)(((y - y0) << log2TW) + (x - x0));
     }
+    // tile-local index of edge position p (top row, bottom row, left column,
+    // right column; corners appear twice)
+    __device__ __forceinline__ int edge_local(int p) const
+    {
+        if (p < TW) return p;
+        if (p < 2 * TW) return ((TH - 1) << log2TW) + (p - TW);
+        if (p < 2 * TW + TH) return (p - 2 * TW) << log2TW;
+        return ((p - 2 * TW - TH) << log2TW) + TW - 1;
+    }
+    __device__ __forceinline__ IT site_of_local(int q) const { return site(q >> log2TW, q & (TW - 1)); }
     // tiles to the right and below (periodic)
     __device__ __forceinline__ int64_t right_tile() const { return (int64_t)ty * ntx + (tx + 1) % ntx; }
     __device__ __forceinline__ int64_t down_tile() const { return (int64_t)((ty + 1) % nty) * ntx + tx; }

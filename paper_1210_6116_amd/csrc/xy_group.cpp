@@ -300,7 +300,7 @@ int xy_group_round(xy_group *g, int64_t max_sweeps, int64_t *ran)
         bool fuse = j + 1 < k;
         for (int32_t s : g->order)
             if ((g->slots[s].done + j + 1) % g->pcc.window == 0) fuse = false;
-        GCHECK(g, enqueue_sweep_lc(g->lc, g->d_reps, n, true, fa, fuse, &ready, g->stream, plain));
+        GCHECK(g, enqueue_sweep_lc(g->lc, g->d_reps, n, fa, fuse, &ready, g->stream, plain));
     }
     GCHECK(g, hipStreamSynchronize(g->stream));
     for (int32_t s : g->order) {

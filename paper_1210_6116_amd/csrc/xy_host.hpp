@@ -24,18 +24,18 @@ int ilog2(int64_t v);
 
 struct Resolved {
     int64_t L, N;
-    int32_t TW, TH, ntx, nty;
+    int32_t TW, TH, ntx, nty, nb;
     int64_t ntiles;
 };
 
 // Per-replica byte layout inside an arena.
 struct RepLayout {
-    size_t c, s, lab[2], bx[2], by[2], coins[2], edge[2], partials, end;
+    size_t c, s, lab[2], bx[2], by[2], bslot[2], node[2], cross[2], edge[2], scoin, partials, end;
 };
 
 struct Plan {
     int32_t n = 0, label_bits = 32, max_th = 1, uniform_tw = -1, uniform_th = -1;
-    bool pingpong = true, big_index = false;
+    bool big_index = false;
     std::vector<Resolved> res;
     std::vector<RepLayout> lay;
     size_t off_reps = 0, off_state = 0, off_tile_rep = 0, off_obs = 0, total = 0;
@@ -47,13 +47,13 @@ int make_plan(const xy_params *p, int32_t n, Plan &P);
 // Descriptor of replica k of plan P whose buffers start at base (layout P.lay[k]).
 void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *base, xy::RepState *st, int64_t tile_base,
                int32_t idx, xy::RepDesc &d);
-// One sweep of every replica in lc: links + tile labels (unless *ready), merge,
-// compression, flip (fused with the next sweep's links when fuse_next and the
-// label buffers are double), finalize.  kind_timer(kind, launch) runs each
+// One sweep of every replica in lc: links + tile labels (unless *ready), merge
+// of the boundary components, flip (fused with the next sweep's links when
+// fuse_next), finalize.  kind_timer(kind, launch) runs each
 // launch (and may bracket it with events).
 template <typename Timer>
-hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int32_t nrep, bool pingpong,
-                            const xy::FlipArgs &fa, bool fuse_next, bool *ready, hipStream_t s, Timer &&timer)
+hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int32_t nrep, const xy::FlipArgs &fa,
+                            bool fuse_next, bool *ready, hipStream_t s, Timer &&timer)
 {
     hipError_t e = hipSuccess;
     if (!*ready) {
@@ -61,11 +61,11 @@ hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int
         if (e != hipSuccess) return e;
     }
     e = timer(XY_K_MERGE, [&] {
-        hipError_t e2 = xy::launch_merge(lc, true, s);
-        return e2 == hipSuccess ? xy::launch_compress(lc, s) : e2;
+        const hipError_t e2 = xy::launch_merge(lc, true, s);
+        return e2 == hipSuccess ? xy::launch_resolve(lc, s) : e2;
     });
     if (e != hipSuccess) return e;
-    const bool fuse = fuse_next && pingpong;
+    const bool fuse = fuse_next;
     if (fuse)
         e = timer(XY_K_FUSED, [&] { return xy::launch_tile(lc, xy::TILE_FUSED, s); });
     else

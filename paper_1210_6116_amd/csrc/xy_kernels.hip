@@ -169,45 +169,69 @@ __device__ void union_lds(uint32_t *lab, uint32_t a, uint32_t b)
     }
 }
 
-// ------------------------------------------------- union-find in global memory
-// Root of v with intermediate pointer jumping: every node on the path is
-// re-pointed at its grandparent.  Parents only ever decrease and stay inside
-// the node's set, so these plain stores are benign even while other threads
-// hook roots: a stale value only shortens less.
-template <typename LT>
-__device__ LT find_jump(LT *lab, LT v)
+// ------------------------------------------- forest of boundary components
+// Entry of node n: (key << 32) | parent.  A root is its own parent; a parent's
+// key is never larger than its child's, so a root carries the smallest key,
+// i.e. the smallest site, of everything united under it.
+
+// Root entry of node n, with intermediate pointer jumping: every node on the
+// path is re-pointed at its grandparent.  An entry only ever moves to an
+// ancestor in the same set and roots are never overwritten, so these plain
+// stores are benign while other threads hook roots; a hook such a store may
+// undo is always followed by the union of the hooked root's former parent.
+__device__ unsigned long long find_jump(unsigned long long *P, uint32_t n)
 {
-    LT par = lab[v];
-    if (par == v) return v;
-    LT prev = v;
+    unsigned long long e = P[n];
+    if ((uint32_t)e == n) return e;
+    uint32_t prev = n;
     while (true) {
-        const LT next = lab[par];
-        if (next == par) return par;
-        lab[prev] = next;
+        const uint32_t par = (uint32_t)e;
+        const unsigned long long g = P[par];
+        if ((uint32_t)g == par) return g;
+        P[prev] = g;
         prev = par;
-        par = next;
+        e = g;
     }
 }
 
-// Lock-free union: the larger root is hooked under the smaller one with an
-// atomic minimum, so every root is the smallest site of its tree.  If the hook
-// target stopped being a root meanwhile, continue with the parent it got.
-template <typename LT>
-__device__ void union_global(LT *lab, LT a, LT b)
+// Lock-free union: the root with the larger key is hooked under the other
+// with a 64-bit atomic minimum.  If the hooked node stopped being a root
+// meanwhile, the union continues with the parent it had got.
+__device__ void union_nodes(unsigned long long *P, uint32_t a, uint32_t b)
 {
     while (true) {
-        a = find_jump(lab, a);
-        b = find_jump(lab, b);
-        if (a == b) return;
-        if (a > b) {
-            const LT tmp = a;
-            a = b;
-            b = tmp;
+        unsigned long long ra = find_jump(P, a), rb = find_jump(P, b);
+        if (ra == rb) return;
+        if (ra > rb) {
+            const unsigned long long tmp = ra;
+            ra = rb;
+            rb = tmp;
         }
-        const LT old = atomicMin(&lab[b], a);
-        if (old == b) return;
-        b = old;
+        const unsigned long long old = atomicMin(&P[(uint32_t)rb], ra);
+        if (old == rb) return;
+        a = (uint32_t)ra;
+        b = (uint32_t)old;
     }
+}
+
+// Key (smallest site) of the cluster of node n; read only.
+__device__ __forceinline__ uint32_t root_key(const unsigned long long *P, uint32_t n)
+{
+    unsigned long long e = P[n];
+    while ((uint32_t)e != n) {
+        n = (uint32_t)e;
+        e = P[n];
+    }
+    return (uint32_t)(e >> 32);
+}
+
+// Flip coin of the cluster whose smallest site is key, in sweep t.
+__device__ __forceinline__ bool coin_of(const RepDesc &R, uint32_t t, uint32_t key)
+{
+    const U4 o = philox4x32_10(key >> 7, R.rep, t, TAG_FLIP, (uint32_t)R.seed, (uint32_t)(R.seed >> 32));
+    const uint32_t wi = (key >> 5) & 3u;
+    const uint32_t w = wi == 0 ? o.x : wi == 1 ? o.y : wi == 2 ? o.z : o.w;
+    return (w >> (key & 31u)) & 1u;
 }
 
 // --------------------------------------------- reductions (fixed order)
@@ -291,13 +315,15 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
 }
 
 // ----------------------------------------------------------- the tile kernel
-// LDS: spin[(TH+1)*(TW+1)] float2 (tile + right halo column + bottom halo row)
+// LDS: spin[(TH+1)*(TW+1)] float2 (tile + right halo column + bottom halo row;
+//        reused for the smallest edge position of every tile-local root)
 //      | bxm[64], bym[64] u64 row masks of active links
+//      | scoin[4], rcoin[64] u64 flip coins of edge slots and of rows
 //      | lab[TW*TH] u32 tile-local union-find (labelling)
 // BT = rows per wave known at compile time (tiles of 64 x 4*BT; every loop
 // over a wave's rows is unrolled and its independent loads are issued
 // together); BT = 0 is the general path for lattices narrower than 64.
-template <typename LT, typename IT, int MODE, int BT>
+template <typename IT, int MODE, int BT>
 __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ reps,
                                                     const uint32_t *__restrict__ tile_rep,
                                                     int32_t nrep, int64_t gtile0)
@@ -316,7 +342,6 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     const int TW = FIXED ? 64 : T.TW, TH = FIXED ? 4 * BT : T.TH, SS = TW + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int B = FIXED ? BT : band_rows(TH), yb = wave * B;
-    const IT Lm = T.L - 1;
     RepState *st = R.st;
     const uint64_t t = st->t;
     const int par = (int)(t & 1);
@@ -328,18 +353,21 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     float2 *spin = (float2 *)smem;
     uint64_t *bxm = (uint64_t *)(spin + (TH + 1) * SS);
     uint64_t *bym = bxm + 64;
-    uint32_t *lab_s = (uint32_t *)(bym + 64);
+    uint64_t *scoin = bym + 64;  // 4 words: coins of the edge slots
+    uint64_t *rcoin = scoin + 4; // 64 words: coins of the tile's rows
+    uint32_t *lab_s = (uint32_t *)(rcoin + 64);
     const int64_t ecount = TH + TW;
     float *__restrict__ cp = R.c;
     float *__restrict__ sp = R.s;
 
     if constexpr (FLIP) {
-        LT *lab = (LT *)R.lab[par];
-        const uint32_t *__restrict__ coins = R.coins[par];
+        const uint16_t *__restrict__ lab = R.lab[par];
+        const uint8_t *__restrict__ bsl = R.bslot[par];
         const double rx = st->dir[par][0], ry = st->dir[par][1];
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
-        auto flip_one = [&](uint32_t coinword, LT root, float c0, float s0, float &c1, float &s1) -> bool {
-            const bool f = (coinword >> (root & 31)) & 1u;
+        const uint32_t tf = (uint32_t)t;
+        const int NB = R.nb;
+        auto flip_one = [&](bool f, float c0, float s0, float &c1, float &s1) -> bool {
             double c = c0, s = s0;
             if (f) {
                 const double g = 2.0 * (c * rx + s * ry);
@@ -355,56 +383,68 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
             s1 = (float)s;
             return f || renorm;
         };
-        // all independent loads of the wave's rows first: parents and spins;
-        // after the merge's compression pass the root of site i is lab[lab[i]]
-        LT pl[BMAX];
+        // all independent loads of the wave's rows first: labels and spins
+        uint32_t lv[BMAX];
         float c0[BMAX], s0[BMAX];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             if (own(k)) {
                 const IT i = T.site(yb + k, lane);
-                pl[k] = lab[i];
+                lv[k] = lab[i];
                 c0[k] = cp[i];
                 s0[k] = sp[i];
             }
         }
         // halo: right column and bottom row of the neighbouring tiles (spins
-        // before the sweep from their edge copies), flipped here exactly as
-        // their owners flip them
-        LT hp = 0;
+        // before the sweep from their edge copies, coins from their edge slots
+        // and slot coins), flipped here exactly as their owners flip them
+        const unsigned long long *__restrict__ sc = R.scoin;
         float2 he = make_float2(0.f, 0.f);
         int hslot = -1;
+        bool hcoin = false;
         if (wave == 0 && lane < TH) {
-            const IT h = ((T.y0 + (IT)lane) << T.log2L) + ((T.x0 + (IT)TW) & Lm);
-            hp = lab[h];
-            he = R.edge[par][T.right_tile() * ecount + lane];
+            const int64_t nt = T.right_tile();
+            const uint32_t sl = bsl[nt * NB + 2 * TW + lane];
+            hcoin = (sc[nt * 4 + (sl >> 6)] >> (sl & 63u)) & 1ull;
+            he = R.edge[par][nt * ecount + lane];
             hslot = lane * SS + TW;
         } else if (wave == 1 && lane < TW) {
-            const IT h = (((T.y0 + (IT)TH) & Lm) << T.log2L) + T.x0 + (IT)lane;
-            hp = lab[h];
-            he = R.edge[par][T.down_tile() * ecount + TH + lane];
+            const int64_t nt = T.down_tile();
+            const uint32_t sl = bsl[nt * NB + lane];
+            hcoin = (sc[nt * 4 + (sl >> 6)] >> (sl & 63u)) & 1ull;
+            he = R.edge[par][nt * ecount + TH + lane];
             hslot = TH * SS + lane;
         }
-        LT root[BMAX];
-#pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (own(k)) root[k] = lab[pl[k]];
-        const LT hroot = hslot >= 0 ? lab[hp] : 0;
-        uint32_t cw[BMAX];
-#pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (own(k)) cw[k] = coins[root[k] >> 5];
+        // coins of the clusters that reach the tile's edge (bit s of scoin: the
+        // slot coins drawn after the merge), and of clusters inside the tile
+        // (rooted at one of its sites): the Philox block holding a row's
+        // sites, bit x of rcoin[y] for site (y, x)
+        if (threadIdx.x < 4) scoin[threadIdx.x] = sc[lt * 4 + threadIdx.x];
+        if (threadIdx.x >= 64 && threadIdx.x < 64 + TH) {
+            const int y = threadIdx.x - 64;
+            const IT site0 = T.site(y, 0);
+            const U4 o = philox4x32_10((uint32_t)(site0 >> 7), R.rep, tf, TAG_FLIP, (uint32_t)R.seed,
+                                       (uint32_t)(R.seed >> 32));
+            const uint32_t wi = (uint32_t)(site0 >> 5) & 3u;
+            const uint32_t ws[4] = {o.x, o.y, o.z, o.w};
+            const uint64_t two = ((uint64_t)(wi < 3 ? ws[wi + 1] : 0u) << 32) | ws[wi];
+            rcoin[y] = two >> ((uint32_t)site0 & 31u);
+        }
         if (hslot >= 0) {
             float c1, s1;
-            flip_one(coins[hroot >> 5], hroot, he.x, he.y, c1, s1);
+            flip_one(hcoin, he.x, he.y, c1, s1);
             spin[hslot] = make_float2(c1, s1);
         }
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             if (own(k)) {
                 const IT i = T.site(yb + k, lane);
+                const uint32_t l = lv[k];
+                const bool f = (l & kBoundary) ? ((scoin[(l & 0xFFu) >> 6] >> (l & 63u)) & 1ull)
+                                               : ((rcoin[l >> T.log2TW] >> (l & (uint32_t)(TW - 1))) & 1ull);
                 float c1, s1;
-                if (flip_one(cw[k], root[k], c0[k], s0[k], c1, s1)) {
+                if (flip_one(f, c0[k], s0[k], c1, s1)) {
                     cp[i] = c1;
                     sp[i] = s1;
                 }
@@ -457,6 +497,9 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
             key1 = (uint32_t)(R.seed >> 32);
         }
         U4 w = {0u, 0u, 0u, 0u};
+        // a row's values below are the next row's own: carried, not recomputed
+        double cdn = 0.0, sdn = 0.0;
+        float adn = 0.0f;
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int y = yb + k;
@@ -467,13 +510,18 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
                 const float2 r = spin[y * SS + lane + 1];
                 const float2 d = spin[(y + 1) * SS + lane];
                 if constexpr (FLIP) {
-                    const double ci = a.x, si = a.y, cr = r.x, sr = r.y, cd = d.x, sd = d.y;
-                    v[0] += ci * cr + si * sr;
-                    v[1] += si * cr - ci * sr;
-                    v[2] += ci * cd + si * sd;
-                    v[3] += si * cd - ci * sd;
+                    // FP64 link sums; fused multiply-adds (the sums are compared
+                    // with a tolerance, not bit for bit)
+                    const double ci = k == 0 ? (double)a.x : cdn, si = k == 0 ? (double)a.y : sdn;
+                    const double cr = r.x, sr = r.y, cd = d.x, sd = d.y;
+                    v[0] = fma(ci, cr, fma(si, sr, v[0]));
+                    v[1] = fma(si, cr, fma(-ci, sr, v[1]));
+                    v[2] = fma(ci, cd, fma(si, sd, v[2]));
+                    v[3] = fma(si, cd, fma(-ci, sd, v[3]));
                     v[4] += ci;
                     v[5] += si;
+                    cdn = cd;
+                    sdn = sd;
                 }
                 if constexpr (BONDS) {
                     const IT gy = T.y0 + (IT)y;
@@ -483,9 +531,10 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
                                           (uint32_t)tb, TAG_BOND, key0, key1);
                     const uint32_t wx = (gy & 1) ? w.z : w.x;
                     const uint32_t wy = (gy & 1) ? w.w : w.y;
-                    const float ai = a.x * ctx.rxf + a.y * ctx.ryf;
+                    const float ai = k == 0 ? a.x * ctx.rxf + a.y * ctx.ryf : adn;
                     const float ar = r.x * ctx.rxf + r.y * ctx.ryf;
                     const float ad = d.x * ctx.rxf + d.y * ctx.ryf;
+                    adn = ad;
                     xa = bond_decide(ctx, ai, ar, wx, a, r);
                     ya = bond_decide(ctx, ai, ad, wy, a, d);
                 }
@@ -547,24 +596,6 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
                 gby[word] = vy;
             }
         }
-        // flip-coin table of sweep tb: this tile's share of the N/128 blocks
-        uint32_t *coins = R.coins[pb];
-        if (R.N >= 128) {
-            const int nc = (TW * TH) >> 7;
-            for (int j = threadIdx.x; j < nc; j += kThreads) {
-                const int64_t cb = lt * nc + j;
-                const U4 o = philox4x32_10((uint32_t)cb, R.rep, (uint32_t)tb, TAG_FLIP, (uint32_t)R.seed,
-                                           (uint32_t)(R.seed >> 32));
-                *(uint4 *)(coins + cb * 4) = make_uint4(o.x, o.y, o.z, o.w);
-            }
-        } else if (lt == 0 && threadIdx.x == 0) {
-            const U4 o = philox4x32_10(0u, R.rep, (uint32_t)tb, TAG_FLIP, (uint32_t)R.seed,
-                                       (uint32_t)(R.seed >> 32));
-            coins[0] = o.x;
-            coins[1] = o.y;
-            coins[2] = o.z;
-            coins[3] = o.w;
-        }
     }
 
     // ---- in-tile labelling of sweep tb
@@ -619,32 +650,67 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
         }
     }
     __syncthreads();
-    // 3) tile-local roots as global site indices
-    LT *labn = (LT *)R.lab[pb];
+    // 3) tile-local roots; every site's entry is then its root
     uint32_t lr[BMAX];
 #pragma unroll
     for (int k = 0; k < B; ++k)
         if (own(k)) lr[k] = find_lds(lab_s, (uint32_t)((yb + k) * TW + lane));
+    __syncthreads();
+    uint32_t *smin = (uint32_t *)smem;  // smallest edge position per root (spin area, free now)
 #pragma unroll
-    for (int k = 0; k < B; ++k)
-        if (own(k))
-            labn[T.site(yb + k, lane)] = (LT)T.site((int)(lr[k] >> T.log2TW), (int)(lr[k] & (TW - 1)));
+    for (int k = 0; k < B; ++k) {
+        if (own(k)) {
+            const uint32_t q = (uint32_t)((yb + k) * TW + lane);
+            lab_s[q] = lr[k];
+            if (lr[k] == q) smin[q] = NONE;
+        }
+    }
+    __syncthreads();
+    // 4) components reaching the tile's edge: slot = smallest edge position
+    const int NB = R.nb;
+    const int p = threadIdx.x;  // NB <= 256 edge positions, one per thread
+    uint32_t proot = 0;
+    if (p < NB) {
+        proot = lab_s[T.edge_local(p)];
+        atomicMin(&smin[proot], (uint32_t)p);
+    }
+    __syncthreads();
+    if (p < NB) {
+        const uint32_t sl = smin[proot];
+        const int64_t nbase = lt * NB;
+        R.bslot[pb][nbase + p] = (uint8_t)sl;
+        if (sl == (uint32_t)p)
+            R.node[pb][nbase + p] =
+                ((unsigned long long)(uint32_t)T.site_of_local((int)proot) << 32) | (uint32_t)(nbase + p);
+    }
+    // 5) tile-local labels, and the links over the right and bottom edges
+    uint16_t *labn = R.lab[pb];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        if (own(k)) {
+            const uint32_t sl = smin[lr[k]];
+            labn[T.site(yb + k, lane)] = (uint16_t)(sl != NONE ? (kBoundary | sl) : lr[k]);
+        }
+    }
+    if (wave == 0) {
+        const bool xr = lane < TH && ((bxm[lane] >> (TW - 1)) & 1ull);
+        const uint64_t xm = __ballot(xr);
+        if (lane == 0) {
+            R.cross[pb][2 * lt] = xm;
+            R.cross[pb][2 * lt + 1] = bym[TH - 1] & twmask;
+        }
+    }
 }
 
 // ------------------------------------------------- merge across tiles
-// One wave per (tile, edge): edge 0 = links leaving the right column, edge 1 =
-// links leaving the bottom row.  Also computes the mirror direction of the
-// next sweep (tile 0 of each replica).
-// COMPRESS (a second launch, after every union has finished): both end sites
-// of every active edge link and the labels read from them are pointed straight
-// at their final root.  Every tile-local root of a cluster that crosses a tile
-// edge is such an end site or end label, so afterwards the root of any site i
-// is lab[lab[i]].
-template <typename LT, typename IT, bool COMPRESS>
+// One wave per tile edge (0: right, TH links; 1: bottom, TW links).  Every
+// active link over the edge unites the boundary nodes of its two end
+// components; a link whose pair equals the previous lane's is skipped.  Reads
+// are contiguous (the edge's link mask and the two rows of edge slots); the
+// unions touch only the forest of boundary nodes.
 __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ reps,
-                                                     const uint32_t *__restrict__ tile_rep,
-                                                     int32_t nrep, int64_t gtile0, int64_t gtile_end,
-                                                     int32_t next_dir)
+                                                     const uint32_t *__restrict__ tile_rep, int32_t nrep,
+                                                     int64_t gtile0, int64_t gtile_end, int32_t next_dir)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
@@ -653,61 +719,49 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
     if (gtile >= gtile_end) return;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
-    const Tile<IT> T = make_tile<IT>(R, lt);
-    const IT Lm = T.L - 1;
+    const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
     const uint64_t t = R.st->t;
     const int par = (int)(t & 1);
-    LT *lab = (LT *)R.lab[par];
-    bool on = false;
-    IT i = 0, j = 0;
-    if (edge == 0) {
-        if (lane < T.TH) {
-            const IT gy = T.y0 + (IT)lane, gx = T.x0 + (IT)T.TW - 1;
-            i = (gy << T.log2L) + gx;
-            on = (R.bx[par][i >> 5] >> (i & 31)) & 1u;
-            j = (gy << T.log2L) + ((gx + 1) & Lm);
-        }
-    } else {
-        if (lane < T.TW) {
-            const IT gy = T.y0 + (IT)T.TH - 1, gx = T.x0 + (IT)lane;
-            i = (gy << T.log2L) + gx;
-            on = (R.by[par][i >> 5] >> (i & 31)) & 1u;
-            j = (((gy + 1) & Lm) << T.log2L) + gx;
-        }
-    }
-    LT a = 0, b = 0;
+    const int NB = R.nb;
+    const uint64_t m = R.cross[par][2 * lt + edge];
+    const bool on = lane < (edge ? T.TW : T.TH) && ((m >> lane) & 1ull);
+    uint32_t a = 0, b = 0;
     if (on) {
-        a = lab[i];
-        b = lab[j];
+        const uint8_t *bsl = R.bslot[par];
+        const int64_t nt = edge ? T.down_tile() : T.right_tile();
+        const int pa = edge ? T.TW + lane : 2 * T.TW + T.TH + lane;  // own bottom row / right column
+        const int pn = edge ? lane : 2 * T.TW + lane;                 // neighbour's top row / left column
+        a = (uint32_t)(lt * NB) + bsl[lt * NB + pa];
+        b = (uint32_t)(nt * NB) + bsl[nt * NB + pn];
     }
-    const LT pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
+    const uint32_t pa = __shfl_up(a, 1), pbv = __shfl_up(b, 1);
     const int pon = __shfl_up((int)on, 1);
-    // the union of a pair equal to the previous lane's is skipped; the
-    // compression pass visits every link, because two different hooked
-    // tile-local roots can read back the same parent
-    const bool dup = !COMPRESS && lane > 0 && pon && pa == a && pb == b;
-    if (on && !dup) {
-        if (COMPRESS) {
-            // The end sites themselves are re-pointed as well: a site that is
-            // its tile-local root and was hooked reads back its new parent.
-            // Writes are atomic minima: the root is the smallest site of its
-            // tree, so a concurrent write of a mere ancestor can never
-            // replace it.
-            LT root = (LT)i;
-            while (true) {
-                const LT p = lab[root];
-                if (p == root) break;
-                root = p;
-            }
-            if (lab[i] != root) atomicMin(&lab[i], root);
-            if (lab[a] != root) atomicMin(&lab[a], root);
-            if (lab[j] != root) atomicMin(&lab[j], root);
-            if (lab[b] != root) atomicMin(&lab[b], root);
-        } else {
-            union_global(lab, a, b);
-        }
-    }
-    if (!COMPRESS && next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
+    const bool dup = lane > 0 && pon && pa == a && pbv == b;
+    if (on && !dup) union_nodes(R.node[par], a, b);
+    if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
+}
+
+// ------------------------------------------------- coins of edge slots
+// After the merge: every used slot (the smallest edge position of its tile
+// component) finds the smallest site of its cluster and draws that cluster's
+// flip coin; bit s of scoin[4 * tile + s / 64] is the coin of slot s.  One
+// block per tile, one thread per edge position.
+__global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict__ reps,
+                                                       const uint32_t *__restrict__ tile_rep, int32_t nrep,
+                                                       int64_t gtile0)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t lt;
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
+    const uint64_t t = R.st->t;
+    const int par = (int)(t & 1);
+    const int NB = R.nb;
+    const int p = threadIdx.x;
+    bool cb = false;
+    if (p < NB && R.bslot[par][lt * NB + p] == (uint8_t)p)
+        cb = coin_of(R, (uint32_t)t, root_key(R.node[par], (uint32_t)(lt * NB + p)));
+    const uint64_t m = __ballot(cb);
+    if (lane == 0) R.scoin[lt * 4 + wave] = m;
 }
 
 // ------------------------------------------------- finalise a sweep
@@ -724,7 +778,20 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restr
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) tot[k] = 0.0;
     const int64_t nt = R.ntiles;
-    for (int64_t j = threadIdx.x; j < nt; j += kFinThreads) {
+    // four tiles per thread per round, their loads issued together
+    int64_t j = threadIdx.x;
+    for (; j + 3 * kFinThreads < nt; j += 4 * kFinThreads) {
+        double x[4][kNumSums];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < kNumSums; ++k) x[q][k] = R.partials[k * nt + j + q * kFinThreads];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < kNumSums; ++k) tot[k] += x[q][k];
+    }
+    for (; j < nt; j += kFinThreads) {
 #pragma unroll
         for (int k = 0; k < kNumSums; ++k) tot[k] += R.partials[k * nt + j];
     }
@@ -832,30 +899,38 @@ __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict_
 }
 
 // ------------------------------------------------- canonical labels
-template <typename LT>
-__global__ __launch_bounds__(kThreads) void k_flatten(const LT *__restrict__ lab, int64_t N, void *out,
-                                                       int32_t out_bits)
+// Label of every site of replica r from slot q: the smallest site of its
+// cluster (tile-local root, or the key of its boundary node's root).
+template <typename IT>
+__global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict__ reps, int32_t r, int32_t q,
+                                                       void *out, int32_t out_bits)
 {
+    const RepDesc &R = reps[r];
     const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < N; i += stride) {
-        LT x = (LT)i;
-        while (true) {
-            const LT p = lab[x];
-            if (p == x) break;
-            x = p;
+    const int log2TH = __ffs(R.TH) - 1;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < R.N; i += stride) {
+        const IT y = (IT)i >> R.log2L, x = (IT)i & (IT)(R.L - 1);
+        const int64_t lt = (int64_t)(y >> log2TH) * R.ntx + (int64_t)(x >> R.log2TW);
+        const uint32_t l = R.lab[q][i];
+        uint64_t key;
+        if (l & kBoundary) {
+            key = root_key(R.node[q], (uint32_t)(lt * R.nb) + (l & 0xFFu));
+        } else {
+            const Tile<IT> T = make_tile<IT>(R, lt);
+            key = (uint64_t)T.site_of_local((int)l);
         }
         if (out_bits == 64)
-            ((uint64_t *)out)[i] = (uint64_t)x;
+            ((uint64_t *)out)[i] = key;
         else
-            ((uint32_t *)out)[i] = (uint32_t)x;
+            ((uint32_t *)out)[i] = (uint32_t)key;
     }
 }
 
 // ====================================================== host-side launchers
-size_t lds_bytes_tile(int TH, int label_bits)
+size_t lds_bytes_tile(int TH)
 {
-    (void)label_bits;
-    return (size_t)(TH + 1) * 65 * sizeof(float2) + 2 * 64 * sizeof(uint64_t) + (size_t)64 * TH * sizeof(uint32_t);
+    return (size_t)(TH + 1) * 65 * sizeof(float2) + (2 * 64 + 4 + 64) * sizeof(uint64_t) +
+           (size_t)64 * TH * sizeof(uint32_t);
 }
 
 // Element-wise kernels over N sites loop with a grid stride: a dispatch holds
@@ -884,19 +959,14 @@ hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s)
 template <int MODE, int BT>
 static void tile_dispatch_bt(const Launch &lc, hipStream_t s)
 {
-    const size_t lds = lds_bytes_tile(lc.max_th, lc.label_bits);
+    const size_t lds = lds_bytes_tile(lc.max_th);
     const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
-    if (lc.label_bits == 64) {
-        if (lc.big_index)
-            hipLaunchKernelGGL((k_tile<unsigned long long, uint64_t, MODE, BT>), grid, block, lds, s, lc.reps,
-                               lc.tile_rep, lc.nrep, lc.gtile0);
-        else
-            hipLaunchKernelGGL((k_tile<unsigned long long, uint32_t, MODE, BT>), grid, block, lds, s, lc.reps,
-                               lc.tile_rep, lc.nrep, lc.gtile0);
-    } else {
-        hipLaunchKernelGGL((k_tile<uint32_t, uint32_t, MODE, BT>), grid, block, lds, s, lc.reps, lc.tile_rep,
-                           lc.nrep, lc.gtile0);
-    }
+    if (lc.big_index)
+        hipLaunchKernelGGL((k_tile<uint64_t, MODE, BT>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
+                           lc.gtile0);
+    else
+        hipLaunchKernelGGL((k_tile<uint32_t, MODE, BT>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
+                           lc.gtile0);
 }
 
 // Fixed-size tiles (64 x 4*BT) when every replica of the launch has that
@@ -926,33 +996,19 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool COMPRESS>
-static void merge_dispatch(const Launch &lc, bool next_dir, hipStream_t s)
+hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s)
 {
     const int64_t waves = 2 * (lc.gtile_end - lc.gtile0);
     const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves)), block(kThreads);
-    if (lc.label_bits == 64) {
-        if (lc.big_index)
-            hipLaunchKernelGGL((k_merge<unsigned long long, uint64_t, COMPRESS>), grid, block, 0, s, lc.reps,
-                               lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
-        else
-            hipLaunchKernelGGL((k_merge<unsigned long long, uint32_t, COMPRESS>), grid, block, 0, s, lc.reps,
-                               lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
-    } else {
-        hipLaunchKernelGGL((k_merge<uint32_t, uint32_t, COMPRESS>), grid, block, 0, s, lc.reps, lc.tile_rep,
-                           lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)next_dir);
-    }
-}
-
-hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s)
-{
-    merge_dispatch<false>(lc, next_dir, s);
+    hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end,
+                       (int32_t)next_dir);
     return hipGetLastError();
 }
 
-hipError_t launch_compress(const Launch &lc, hipStream_t s)
+hipError_t launch_resolve(const Launch &lc, hipStream_t s)
 {
-    merge_dispatch<true>(lc, false, s);
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(lc.gtile_end - lc.gtile0)), dim3(kThreads), 0, s, lc.reps,
+                       lc.tile_rep, lc.nrep, lc.gtile0);
     return hipGetLastError();
 }
 
@@ -973,16 +1029,16 @@ hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &
     return hipGetLastError();
 }
 
-hipError_t launch_flatten(const void *d_lab, int32_t label_bits, int64_t N, void *d_out, int32_t out_bits,
-                          hipStream_t s)
+hipError_t launch_flatten(const RepDesc *d_reps, int32_t r, int32_t slot, int64_t N, bool big_index, void *d_out,
+                          int32_t out_bits, hipStream_t s)
 {
     const int64_t blocks = std::min<int64_t>((N + kThreads - 1) / kThreads, kMaxStrideBlocks);
-    if (label_bits == 64)
-        hipLaunchKernelGGL((k_flatten<unsigned long long>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                           (const unsigned long long *)d_lab, N, d_out, out_bits);
+    if (big_index)
+        hipLaunchKernelGGL((k_flatten<uint64_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, slot,
+                           d_out, out_bits);
     else
-        hipLaunchKernelGGL((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                           (const uint32_t *)d_lab, N, d_out, out_bits);
+        hipLaunchKernelGGL((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, slot,
+                           d_out, out_bits);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ struct Launch {
     const RepDesc *reps;      // device array of replica descriptors
     const uint32_t *tile_rep; // device: replica of every global tile (unused if nrep == 1)
     int32_t nrep;
-    int32_t label_bits;       // 32 or 64
+    int32_t label_bits;       // width of canonical labels handed out: 32 or 64
     int32_t max_th;           // largest tile height among the replicas (LDS sizing)
     int32_t big_index;        // 1: 64-bit site indices (some replica has N > 2^30)
     int32_t uniform_tw, uniform_th;  // tile shape shared by every replica, or 0
@@ -44,12 +44,14 @@ hipError_t launch_edge_refresh(const RepDesc *d_reps, int32_t r, int64_t ntiles,
 hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s);
 hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s);
 hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s);
-hipError_t launch_compress(const Launch &lc, hipStream_t s);
+hipError_t launch_resolve(const Launch &lc, hipStream_t s);
 hipError_t launch_measure(const Launch &lc, hipStream_t s);
 hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out,
                            hipStream_t s);
-hipError_t launch_flatten(const void *d_lab, int32_t label_bits, int64_t N, void *d_out, int32_t out_bits,
-                          hipStream_t s);
-size_t lds_bytes_tile(int TH, int label_bits);
+// Canonical labels (smallest site of each cluster) of replica r from label slot
+// `slot`, as N values of out_bits (32 or 64) into d_out.
+hipError_t launch_flatten(const RepDesc *d_reps, int32_t r, int32_t slot, int64_t N, bool big_index, void *d_out,
+                          int32_t out_bits, hipStream_t s);
+size_t lds_bytes_tile(int TH);
 
 }  // namespace xy

@@ -44,8 +44,9 @@ def test_bytes_required_and_argument_errors():
     assert n64 > 64 * 64 * 8
     big = _lib.xy_params(L=65536, beta=1.0, seed=1, replica=0, label_bits=0, start=0, tile_rows=0)
     nbig = _lib.xy_bytes_required([big])
-    # spins (8 B) + one uint64 label forest (8 B) per site, and less than 288 GB
-    assert 16 * 65536 ** 2 < nbig < 288e9
+    # spins (8 B) + two planes of 16-bit tile-local labels (4 B) per site, and
+    # well inside 288 GB
+    assert 12 * 65536 ** 2 < nbig < 100e9
     for bad in (dict(L=48), dict(L=1), dict(L=131072), dict(beta=-1.0), dict(label_bits=16),
                 dict(L=65536, label_bits=32), dict(tile_rows=8), dict(start=7)):
         kw = dict(L=64, beta=1.0, seed=1, replica=0, label_bits=0, start=0, tile_rows=0)

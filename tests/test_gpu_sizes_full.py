@@ -10,10 +10,10 @@ oracle cannot hold it, so the sweep is checked
   * on a seeded sample of links and sites that the oracle decides one by one:
     link decisions from the pre-sweep spins (bit-exact) and reflections of the
     sampled sites given their cluster roots (bit-exact);
-  * everywhere, on the device, by properties that hold at any size: every root
-    is a fixed point of the forest and no larger than its sites; the two ends
-    of every active link share a root; spins stay unit vectors; and the
-    observables equal an FP64 recomputation of the sums from the state.
+  * everywhere, on the device, by properties of the canonical labels that hold
+    at any size: a site's label is no larger than the site and labels itself;
+    the two ends of every active link share a label; spins stay unit vectors;
+    and the observables equal an FP64 recomputation of the sums from the state.
 Whether two distinct components were wrongly united is not decided at this
 size (that needs a labelling of the whole lattice); the small-size parity
 tests decide it exactly.
@@ -62,10 +62,6 @@ def _bits(words: torch.Tensor, lo: int, n: int) -> torch.Tensor:
     return ((w.unsqueeze(1) >> sh) & 1).reshape(-1).bool()
 
 
-def _roots(lab: torch.Tensor, idx: torch.Tensor) -> torch.Tensor:
-    return lab.index_select(0, lab.index_select(0, idx))
-
-
 def test_l65536_sampled_oracle_and_invariants():
     import paper_1210_6116_amd as xy
     L, beta, seed, rep = 65536, 1.12, wl.SEED_L65536, 0
@@ -105,7 +101,8 @@ def test_l65536_sampled_oracle_and_invariants():
     torch.cuda.synchronize()
     v = lat.views()
     assert v["sweep"] == 2
-    lab, bxw, byw = v["labels"], v["bx"], v["by"]
+    bxw, byw = v["bx"], v["by"]
+    lab = lat.labels_device(bits=64)  # canonical: the smallest site of each cluster
 
     # 1. sampled link decisions against the oracle, from the pre-sweep spins
     def gather_bits(words, ix):
@@ -124,7 +121,7 @@ def test_l65536_sampled_oracle_and_invariants():
     assert gx.sum() > 0 and gy.sum() > 0
 
     # 2. sampled reflections: the oracle flips the sampled sites given their roots
-    roots_i = _roots(lab, di)
+    roots_i = lab.index_select(0, di)
     side = int(np.sqrt(n))
     m = side * side
     ri = roots_i.cpu().numpy()
@@ -145,22 +142,18 @@ def test_l65536_sampled_oracle_and_invariants():
         if ar_cache is None:
             ar_cache = torch.arange(cnt, device=dev, dtype=torch.int64)
         idx = ar_cache + lo
-        first = lab[lo:lo + cnt].long()
-        assert bool((first <= idx).all()), y0
-        root = lab.index_select(0, first).long()
-        assert bool((lab.index_select(0, root).long() == root).all()), y0
+        root = lab[lo:lo + cnt]
         assert bool((root <= idx).all()), y0
+        assert bool((lab.index_select(0, root) == root).all()), y0
         rr = root.view(rows, L)
         ax = _bits(bxw, lo, cnt).view(rows, L)
         assert bool((rr[ax] == rr.roll(-1, dims=1)[ax]).all()), ("x links", y0)
         y1 = (y0 + rows) % L
-        below_first = lab[y1 * L:(y1 + 1) * L].long()
-        below = lab.index_select(0, below_first).long()
-        down_roots = torch.cat([rr[1:], below.view(1, L)], dim=0)
+        down_roots = torch.cat([rr[1:], lab[y1 * L:(y1 + 1) * L].view(1, L)], dim=0)
         ay = _bits(byw, lo, cnt).view(rows, L)
         assert bool((rr[ay] == down_roots[ay]).all()), ("y links", y0)
         n_active += int(ax.sum()) + int(ay.sum())
-        del first, root, rr, ax, ay, below, below_first, down_roots, idx
+        del root, rr, ax, ay, down_roots, idx
     assert 0 < n_active < 2 * N
 
     # 4. unit spins and observables from an FP64 recomputation of the sums
@@ -188,6 +181,7 @@ def test_l65536_sampled_oracle_and_invariants():
     for name in NAMES:
         assert abs(float(g[name]) - ref[name]) <= OBS_TOL, (name, float(g[name]), ref[name])
     assert -2.0 < float(g["E"]) < 0.0
+    del v, lab, bxw, byw, c, s
     lat.close()
-    del lat, v, lab, bxw, byw, c, s
+    del lat
     torch.cuda.empty_cache()
