@@ -29,6 +29,28 @@ constexpr int kMaxAttempts = 16;      // rejection draws (two candidates each)
 constexpr uint64_t kRenormEvery = 1024;  // spins rescaled to unit length after sweeps t with (t+1) % this == 0
 constexpr double kTieEps = 1e-9;         // |u - p| below this counts as a near tie
 
+// Global-memory view of a pointer.  Data reached through a descriptor would
+// otherwise be accessed with flat instructions, whose completion is counted
+// together with LDS traffic (every LDS wait would also wait for them).
+#define XY_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ XY_G T *gmem(T *p)
+{
+    return (XY_G T *)p;
+}
+
+__device__ __forceinline__ float2 ldf2(const XY_G float2 *p)
+{
+    const unsigned long long u = *(const XY_G unsigned long long *)p;
+    return make_float2(__uint_as_float((uint32_t)u), __uint_as_float((uint32_t)(u >> 32)));
+}
+
+__device__ __forceinline__ void stf2(XY_G float2 *p, float2 v)
+{
+    *(XY_G unsigned long long *)p =
+        ((unsigned long long)__float_as_uint(v.y) << 32) | (unsigned long long)__float_as_uint(v.x);
+}
+
 struct U4 {
     uint32_t x, y, z, w;
 };

@@ -179,7 +179,7 @@ __device__ void union_lds(uint32_t *lab, uint32_t a, uint32_t b)
 // ancestor in the same set and roots are never overwritten, so these plain
 // stores are benign while other threads hook roots; a hook such a store may
 // undo is always followed by the union of the hooked root's former parent.
-__device__ unsigned long long find_jump(unsigned long long *P, uint32_t n)
+__device__ unsigned long long find_jump(XY_G unsigned long long *P, uint32_t n)
 {
     unsigned long long e = P[n];
     if ((uint32_t)e == n) return e;
@@ -197,7 +197,7 @@ __device__ unsigned long long find_jump(unsigned long long *P, uint32_t n)
 // Lock-free union: the root with the larger key is hooked under the other
 // with a 64-bit atomic minimum.  If the hooked node stopped being a root
 // meanwhile, the union continues with the parent it had got.
-__device__ void union_nodes(unsigned long long *P, uint32_t a, uint32_t b)
+__device__ void union_nodes(XY_G unsigned long long *P, uint32_t a, uint32_t b)
 {
     while (true) {
         unsigned long long ra = find_jump(P, a), rb = find_jump(P, b);
@@ -207,7 +207,8 @@ __device__ void union_nodes(unsigned long long *P, uint32_t a, uint32_t b)
             ra = rb;
             rb = tmp;
         }
-        const unsigned long long old = atomicMin(&P[(uint32_t)rb], ra);
+        const unsigned long long old =
+            __hip_atomic_fetch_min(&P[(uint32_t)rb], ra, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == rb) return;
         a = (uint32_t)ra;
         b = (uint32_t)old;
@@ -215,7 +216,7 @@ __device__ void union_nodes(unsigned long long *P, uint32_t a, uint32_t b)
 }
 
 // Key (smallest site) of the cluster of node n; read only.
-__device__ __forceinline__ uint32_t root_key(const unsigned long long *P, uint32_t n)
+__device__ __forceinline__ uint32_t root_key(const XY_G unsigned long long *P, uint32_t n)
 {
     unsigned long long e = P[n];
     while ((uint32_t)e != n) {
@@ -263,7 +264,7 @@ __device__ __forceinline__ void store_partials(const RepDesc &R, int64_t lt, con
 {
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < kNumSums; ++k) R.partials[k * R.ntiles + lt] = v[k];
+        for (int k = 0; k < kNumSums; ++k) gmem(R.partials)[k * R.ntiles + lt] = v[k];
     }
 }
 
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     const int TW = FIXED ? 64 : T.TW, TH = FIXED ? 4 * BT : T.TH, SS = TW + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int B = FIXED ? BT : band_rows(TH), yb = wave * B;
-    RepState *st = R.st;
+    XY_G RepState *st = gmem(R.st);
     const uint64_t t = st->t;
     const int par = (int)(t & 1);
     const uint64_t tb = MODE == M_FUSED ? t + 1 : t;  // sweep whose links this launch activates
@@ -357,12 +358,13 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     uint64_t *rcoin = scoin + 4; // 64 words: coins of the tile's rows
     uint32_t *lab_s = (uint32_t *)(rcoin + 64);
     const int64_t ecount = TH + TW;
-    float *__restrict__ cp = R.c;
-    float *__restrict__ sp = R.s;
+    XY_G float *__restrict__ cp = gmem(R.c);
+    XY_G float *__restrict__ sp = gmem(R.s);
 
     if constexpr (FLIP) {
-        const uint16_t *__restrict__ lab = R.lab[par];
-        const uint8_t *__restrict__ bsl = R.bslot[par];
+        const XY_G uint16_t *__restrict__ lab = gmem(R.lab[par]);
+        const XY_G uint8_t *__restrict__ bsl = gmem(R.bslot[par]);
+        const XY_G float2 *__restrict__ eg = gmem(R.edge[par]);
         const double rx = st->dir[par][0], ry = st->dir[par][1];
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
         const uint32_t tf = (uint32_t)t;
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
         // halo: right column and bottom row of the neighbouring tiles (spins
         // before the sweep from their edge copies, coins from their edge slots
         // and slot coins), flipped here exactly as their owners flip them
-        const unsigned long long *__restrict__ sc = R.scoin;
+        const XY_G unsigned long long *__restrict__ sc = gmem(R.scoin);
         float2 he = make_float2(0.f, 0.f);
         int hslot = -1;
         bool hcoin = false;
@@ -406,13 +408,13 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
             const int64_t nt = T.right_tile();
             const uint32_t sl = bsl[nt * NB + 2 * TW + lane];
             hcoin = (sc[nt * 4 + (sl >> 6)] >> (sl & 63u)) & 1ull;
-            he = R.edge[par][nt * ecount + lane];
+            he = ldf2(eg + nt * ecount + lane);
             hslot = lane * SS + TW;
         } else if (wave == 1 && lane < TW) {
             const int64_t nt = T.down_tile();
             const uint32_t sl = bsl[nt * NB + lane];
             hcoin = (sc[nt * 4 + (sl >> 6)] >> (sl & 63u)) & 1ull;
-            he = R.edge[par][nt * ecount + TH + lane];
+            he = ldf2(eg + nt * ecount + TH + lane);
             hslot = TH * SS + lane;
         }
         // coins of the clusters that reach the tile's edge (bit s of scoin: the
@@ -453,11 +455,11 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
         }
         __syncthreads();
         // edge copies (first column, first row) of the flipped tile for sweep t+1
-        float2 *en = R.edge[par ^ 1] + lt * ecount;
+        XY_G float2 *en = gmem(R.edge[par ^ 1]) + lt * ecount;
         if (wave == 2 && lane < TH)
-            en[lane] = spin[lane * SS];
+            stf2(en + lane, spin[lane * SS]);
         else if (wave == 3 && lane < TW)
-            en[TH + lane] = spin[lane];
+            stf2(en + TH + lane, spin[lane]);
     } else if constexpr (MODE == M_BONDS) {
         // spins before the sweep: own sites from the planes, halo from edge copies
         float c0[BMAX], s0[BMAX];
@@ -469,10 +471,11 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
                 s0[k] = sp[i];
             }
         }
+        const XY_G float2 *__restrict__ eg = gmem(R.edge[par]);
         if (wave == 0 && lane < TW)
-            spin[TH * SS + lane] = R.edge[par][T.down_tile() * ecount + TH + lane];
+            spin[TH * SS + lane] = ldf2(eg + T.down_tile() * ecount + TH + lane);
         else if (wave == 1 && lane < TH)
-            spin[lane * SS + TW] = R.edge[par][T.right_tile() * ecount + lane];
+            spin[lane * SS + TW] = ldf2(eg + T.right_tile() * ecount + lane);
 #pragma unroll
         for (int k = 0; k < B; ++k)
             if (own(k)) spin[(yb + k) * SS + lane] = make_float2(c0[k], s0[k]);
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
             ctx.ryf = (float)ctx.ry;
             ctx.b2f = (float)(2.0 * ctx.beta);
             ctx.guard = 1e-5f * (1.0f + (float)ctx.beta);
-            ctx.ties = &st->ties[pb];
+            ctx.ties = (unsigned long long *)&st->ties[pb];
             key0 = (uint32_t)R.seed;
             key1 = (uint32_t)(R.seed >> 32);
         }
@@ -553,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
         store_partials(R, lt, v);
     }
     if constexpr (MODE == M_PLANES) {
-        const uint32_t *gbx = R.bx[pb], *gby = R.by[pb];
+        const XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
         for (int y = threadIdx.x; y < TH; y += kThreads) {
             uint64_t mx = 0, my = 0;
             for (int x = 0; x < TW; ++x) {
@@ -570,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     __syncthreads();
     if constexpr (BONDS) {
         // active-link bit planes of sweep tb
-        uint32_t *gbx = R.bx[pb], *gby = R.by[pb];
+        XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
         if (TW == 64) {
             for (int j = threadIdx.x; j < 2 * TH; j += kThreads) {
                 const int y = j >> 1, half = j & 1;
@@ -599,7 +602,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     }
 
     // ---- in-tile labelling of sweep tb
-    const uint64_t twmask = TW == 64 ? ~0ull : ((1ull << TW) - 1ull);
+    const uint64_t twmask = TW == 64 ? ~0ull : ((1ull << (TW & 63)) - 1ull);
     const uint64_t inner = twmask >> 1;  // link x -> x+1 stays inside the tile
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t NONE = 0xFFFFFFFFu;
@@ -678,13 +681,13 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     if (p < NB) {
         const uint32_t sl = smin[proot];
         const int64_t nbase = lt * NB;
-        R.bslot[pb][nbase + p] = (uint8_t)sl;
+        gmem(R.bslot[pb])[nbase + p] = (uint8_t)sl;
         if (sl == (uint32_t)p)
-            R.node[pb][nbase + p] =
+            gmem(R.node[pb])[nbase + p] =
                 ((unsigned long long)(uint32_t)T.site_of_local((int)proot) << 32) | (uint32_t)(nbase + p);
     }
     // 5) tile-local labels, and the links over the right and bottom edges
-    uint16_t *labn = R.lab[pb];
+    XY_G uint16_t *labn = gmem(R.lab[pb]);
 #pragma unroll
     for (int k = 0; k < B; ++k) {
         if (own(k)) {
@@ -696,8 +699,9 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
         const bool xr = lane < TH && ((bxm[lane] >> (TW - 1)) & 1ull);
         const uint64_t xm = __ballot(xr);
         if (lane == 0) {
-            R.cross[pb][2 * lt] = xm;
-            R.cross[pb][2 * lt + 1] = bym[TH - 1] & twmask;
+            XY_G unsigned long long *cr = gmem(R.cross[pb]);
+            cr[2 * lt] = xm;
+            cr[2 * lt + 1] = bym[TH - 1] & twmask;
         }
     }
 }
@@ -720,14 +724,14 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
     const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
-    const uint64_t t = R.st->t;
+    const uint64_t t = gmem(R.st)->t;
     const int par = (int)(t & 1);
     const int NB = R.nb;
-    const uint64_t m = R.cross[par][2 * lt + edge];
+    const uint64_t m = gmem(R.cross[par])[2 * lt + edge];
     const bool on = lane < (edge ? T.TW : T.TH) && ((m >> lane) & 1ull);
     uint32_t a = 0, b = 0;
     if (on) {
-        const uint8_t *bsl = R.bslot[par];
+        const XY_G uint8_t *bsl = gmem(R.bslot[par]);
         const int64_t nt = edge ? T.down_tile() : T.right_tile();
         const int pa = edge ? T.TW + lane : 2 * T.TW + T.TH + lane;  // own bottom row / right column
         const int pn = edge ? lane : 2 * T.TW + lane;                 // neighbour's top row / left column
@@ -737,7 +741,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
     const uint32_t pa = __shfl_up(a, 1), pbv = __shfl_up(b, 1);
     const int pon = __shfl_up((int)on, 1);
     const bool dup = lane > 0 && pon && pa == a && pbv == b;
-    if (on && !dup) union_nodes(R.node[par], a, b);
+    if (on && !dup) union_nodes(gmem(R.node[par]), a, b);
     if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
 }
 
@@ -753,15 +757,15 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
-    const uint64_t t = R.st->t;
+    const uint64_t t = gmem(R.st)->t;
     const int par = (int)(t & 1);
     const int NB = R.nb;
     const int p = threadIdx.x;
     bool cb = false;
-    if (p < NB && R.bslot[par][lt * NB + p] == (uint8_t)p)
-        cb = coin_of(R, (uint32_t)t, root_key(R.node[par], (uint32_t)(lt * NB + p)));
+    if (p < NB && gmem(R.bslot[par])[lt * NB + p] == (uint8_t)p)
+        cb = coin_of(R, (uint32_t)t, root_key(gmem(R.node[par]), (uint32_t)(lt * NB + p)));
     const uint64_t m = __ballot(cb);
-    if (lane == 0) R.scoin[lt * 4 + wave] = m;
+    if (lane == 0) gmem(R.scoin)[lt * 4 + wave] = m;
 }
 
 // ------------------------------------------------- finalise a sweep
@@ -785,7 +789,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restr
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int k = 0; k < kNumSums; ++k) x[q][k] = R.partials[k * nt + j + q * kFinThreads];
+            for (int k = 0; k < kNumSums; ++k) x[q][k] = gmem(R.partials)[k * nt + j + q * kFinThreads];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -793,7 +797,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restr
     }
     for (; j < nt; j += kFinThreads) {
 #pragma unroll
-        for (int k = 0; k < kNumSums; ++k) tot[k] += R.partials[k * nt + j];
+        for (int k = 0; k < kNumSums; ++k) tot[k] += gmem(R.partials)[k * nt + j];
     }
     block_sum<kNumSums, kFinThreads / 64>(tot, red);
     if (threadIdx.x != 0) return;
@@ -911,18 +915,18 @@ __global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict_
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < R.N; i += stride) {
         const IT y = (IT)i >> R.log2L, x = (IT)i & (IT)(R.L - 1);
         const int64_t lt = (int64_t)(y >> log2TH) * R.ntx + (int64_t)(x >> R.log2TW);
-        const uint32_t l = R.lab[q][i];
+        const uint32_t l = gmem(R.lab[q])[i];
         uint64_t key;
         if (l & kBoundary) {
-            key = root_key(R.node[q], (uint32_t)(lt * R.nb) + (l & 0xFFu));
+            key = root_key(gmem(R.node[q]), (uint32_t)(lt * R.nb) + (l & 0xFFu));
         } else {
             const Tile<IT> T = make_tile<IT>(R, lt);
             key = (uint64_t)T.site_of_local((int)l);
         }
         if (out_bits == 64)
-            ((uint64_t *)out)[i] = key;
+            gmem((uint64_t *)out)[i] = key;
         else
-            ((uint32_t *)out)[i] = (uint32_t)key;
+            gmem((uint32_t *)out)[i] = (uint32_t)key;
     }
 }
 
