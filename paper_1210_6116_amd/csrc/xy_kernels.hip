@@ -321,11 +321,12 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
 //      | bxm[64], bym[64] u64 row masks of active links
 //      | scoin[4], rcoin[64] u64 flip coins of edge slots and of rows
 //      | lab[TW*TH] u32 tile-local union-find (labelling)
-// BT = rows per wave known at compile time (tiles of 64 x 4*BT; every loop
-// over a wave's rows is unrolled and its independent loads are issued
-// together); BT = 0 is the general path for lattices narrower than 64.
-template <typename IT, int MODE, int BT>
-__global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ reps,
+// BT = rows per wave known at compile time (tiles of 64 x NW*BT for NW waves;
+// every loop over a wave's rows is unrolled and its independent loads are
+// issued together); BT = 0 is the general path (4 waves) for lattices
+// narrower than 64 and for batches of mixed tile shapes.
+template <typename IT, int MODE, int BT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ reps,
                                                     const uint32_t *__restrict__ tile_rep,
                                                     int32_t nrep, int64_t gtile0)
 {
@@ -335,12 +336,13 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
     constexpr bool FIXED = BT > 0;
     constexpr int BMAX = FIXED ? BT : 16;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kWaves * kNumSums];
+    constexpr int NT = NW * 64;  // threads of the block: NW waves of BT rows (fixed tiles)
+    __shared__ double red[NW * kNumSums];
 
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
     const Tile<IT> T = make_tile<IT>(R, lt);
-    const int TW = FIXED ? 64 : T.TW, TH = FIXED ? 4 * BT : T.TH, SS = TW + 1;
+    const int TW = FIXED ? 64 : T.TW, TH = FIXED ? NW * BT : T.TH, SS = TW + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int B = FIXED ? BT : band_rows(TH), yb = wave * B;
     XY_G RepState *st = gmem(R.st);
@@ -552,12 +554,12 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
         }
     }
     if constexpr (FLIP) {
-        block_sum<kNumSums, kWaves>(v, red);
+        block_sum<kNumSums, NW>(v, red);
         store_partials(R, lt, v);
     }
     if constexpr (MODE == M_PLANES) {
         const XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
-        for (int y = threadIdx.x; y < TH; y += kThreads) {
+        for (int y = threadIdx.x; y < TH; y += NT) {
             uint64_t mx = 0, my = 0;
             for (int x = 0; x < TW; ++x) {
                 const IT i = T.site(y, x);
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
         // active-link bit planes of sweep tb
         XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
         if (TW == 64) {
-            for (int j = threadIdx.x; j < 2 * TH; j += kThreads) {
+            for (int j = threadIdx.x; j < 2 * TH; j += NT) {
                 const int y = j >> 1, half = j & 1;
                 const IT word = (T.site(y, 0) >> 5) + (IT)half;
                 gbx[word] = (uint32_t)(bxm[y] >> (32 * half));
@@ -585,7 +587,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const RepDesc *__restrict__ r
             // narrow lattice (L < 64): the tile spans whole rows, so whole words
             const int nbits = TW * TH;
             const int nwords = nbits >= 32 ? nbits >> 5 : 1;
-            for (int j = threadIdx.x; j < nwords; j += kThreads) {
+            for (int j = threadIdx.x; j < nwords; j += NT) {
                 uint32_t vx = 0u, vy = 0u;
                 for (int b = 0; b < 32; ++b) {
                     const int p = j * 32 + b;
@@ -960,32 +962,33 @@ hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int MODE, int BT>
+template <int MODE, int BT, int NW>
 static void tile_dispatch_bt(const Launch &lc, hipStream_t s)
 {
     const size_t lds = lds_bytes_tile(lc.max_th);
-    const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
+    const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(NW * 64);
     if (lc.big_index)
-        hipLaunchKernelGGL((k_tile<uint64_t, MODE, BT>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
+        hipLaunchKernelGGL((k_tile<uint64_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
                            lc.gtile0);
     else
-        hipLaunchKernelGGL((k_tile<uint32_t, MODE, BT>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
+        hipLaunchKernelGGL((k_tile<uint32_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
                            lc.gtile0);
 }
 
-// Fixed-size tiles (64 x 4*BT) when every replica of the launch has that
-// shape; the general path otherwise.
+// Fixed-size tiles of 64 columns when every replica of the launch has that
+// shape: 8 rows per wave, 4 waves (32 rows) or 8 waves (64 rows), or 4 rows per
+// wave for 16-row tiles; the general path (4 waves) otherwise.
 template <int MODE>
 static void tile_dispatch(const Launch &lc, hipStream_t s)
 {
     if (MODE != M_PLANES && lc.uniform_th == 64 && lc.uniform_tw == 64)
-        tile_dispatch_bt<MODE, 16>(lc, s);
+        tile_dispatch_bt<MODE, 8, 8>(lc, s);
     else if (MODE != M_PLANES && lc.uniform_th == 32 && lc.uniform_tw == 64)
-        tile_dispatch_bt<MODE, 8>(lc, s);
+        tile_dispatch_bt<MODE, 8, 4>(lc, s);
     else if (MODE != M_PLANES && lc.uniform_th == 16 && lc.uniform_tw == 64)
-        tile_dispatch_bt<MODE, 4>(lc, s);
+        tile_dispatch_bt<MODE, 4, 4>(lc, s);
     else
-        tile_dispatch_bt<MODE, 0>(lc, s);
+        tile_dispatch_bt<MODE, 0, 4>(lc, s);
 }
 
 hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
