@@ -131,7 +131,7 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
             l.cross[q] = off;
             off = align_up(off + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
         }
-        l.scoin = off;
+        l.ecoin = off;
         off = align_up(off + (size_t)r.ntiles * 4 * sizeof(unsigned long long));
         l.partials = off;
         off = align_up(off + (size_t)r.ntiles * xy::kNumSums * sizeof(double));
@@ -166,7 +166,7 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
         d.cross[q] = reinterpret_cast<unsigned long long *>(A + l.cross[q]);
         d.edge[q] = reinterpret_cast<float2 *>(A + l.edge[q]);
     }
-    d.scoin = reinterpret_cast<unsigned long long *>(A + l.scoin);
+    d.ecoin = reinterpret_cast<unsigned long long *>(A + l.ecoin);
     d.partials = reinterpret_cast<double *>(A + l.partials);
     d.st = st;
     d.L = r.L;
@@ -284,12 +284,12 @@ hipError_t timed(xy_handle *h, int kind, F launch)
     return e;
 }
 
-// Enqueues one sweep of every replica.  The links of the sweep were already
-// activated and labelled inside the tiles when *ready is set (by the previous
-// sweep's fused pass).  fuse_next: the flip of this sweep also activates and
-// labels the links of the next one (allowed only when beta cannot change in
-// between, i.e. not at the end of a PCC window, and with double buffers).
-int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, bool *ready)
+// Enqueues one sweep of every replica (pp carries the launch state between the
+// sweeps of one call).  fuse_next: the flip of this sweep also activates and
+// labels the links of the next one, and its finalisation runs with the next
+// sweep's edge coins (allowed only when beta cannot change in between, i.e.
+// not at the end of a PCC window, and only if another sweep follows).
+int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, Pipe &pp)
 {
     const xy::Launch lc = launch_all(h);
     hipEvent_t sweep_begin = nullptr;
@@ -298,7 +298,7 @@ int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, bool *re
         HIPCHECK(h, hipEventRecord(sweep_begin, h->stream));
     }
     auto timer = [&](int kind, auto launch) { return timed(h, kind, launch); };
-    HIPCHECK(h, enqueue_sweep_lc(lc, h->d_reps, h->plan.n, fa, fuse_next, ready, h->stream, timer));
+    HIPCHECK(h, enqueue_sweep_lc(lc, h->d_reps, h->plan.n, fa, fuse_next, pp, h->stream, timer));
     if (h->timing) {
         xy_handle::Ev ev;
         ev.kind = XY_K_SWEEP;
@@ -452,14 +452,17 @@ int xy_sweep(xy_handle *h, int64_t nsweeps, xy_obs *trace)
     if (rc) return rc;
     if (nsweeps < 0) return fail(XY_EINVAL, "nsweeps=%lld is negative", (long long)nsweeps);
     const int32_t n = h->plan.n;
-    bool ready = false;
+    Pipe pp;
     for (int64_t k = 0; k < nsweeps; ++k) {
         xy::FlipArgs fa = no_pcc(h);
         if (trace) {
             fa.trace = h->d_trace;
             fa.trace_row = k % kTraceChunk;
         }
-        rc = enqueue_sweep(h, fa, k + 1 < nsweeps, &ready);
+        // a sweep whose trace row is copied back right after it is not fused
+        // (its finalisation must not be deferred past the copy)
+        const bool fuse = k + 1 < nsweeps && !(trace && fa.trace_row == kTraceChunk - 1);
+        rc = enqueue_sweep(h, fa, fuse, pp);
         if (rc) return rc;
         if (trace && (fa.trace_row == kTraceChunk - 1 || k == nsweeps - 1)) {
             const int64_t first = k - fa.trace_row;
@@ -484,8 +487,8 @@ int xy_sweep_graph(xy_handle *h, int64_t nsweeps, int64_t replays)
         h->graph_exec = nullptr;
         h->graph = nullptr;
         HIPCHECK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
-        bool ready = false;
-        for (int64_t k = 0; k < nsweeps && rc == XY_OK; ++k) rc = enqueue_sweep(h, no_pcc(h), k + 1 < nsweeps, &ready);
+        Pipe pp;
+        for (int64_t k = 0; k < nsweeps && rc == XY_OK; ++k) rc = enqueue_sweep(h, no_pcc(h), k + 1 < nsweeps, pp);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(h->stream, &graph);
         if (rc) return rc;
@@ -522,7 +525,7 @@ int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_me
         return fail(XY_EINVAL, "bad PCC schedule (dbeta0=%g dbeta_min=%g halve_every=%lld target=%g)",
                     c->dbeta0, c->dbeta_min, (long long)c->halve_every, c->target);
     const int32_t n = h->plan.n;
-    bool ready = false;
+    Pipe pp;
     for (int64_t k = 0; k < nsteps; ++k) {
         for (int64_t w = 0; w < c->window; ++w) {
             xy::FlipArgs fa = no_pcc(h);
@@ -535,7 +538,7 @@ int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_me
                 fa.wmean = h->d_wmean;
                 fa.wrow = k % kTraceChunk;
             }
-            rc = enqueue_sweep(h, fa, w + 1 < c->window, &ready);
+            rc = enqueue_sweep(h, fa, w + 1 < c->window, pp);
             if (rc) return rc;
         }
         const int64_t row = k % kTraceChunk;

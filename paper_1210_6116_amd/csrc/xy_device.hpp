@@ -85,7 +85,8 @@ constexpr int kNumSums = 6;  // Scx, Ssx, Scy, Ssy, sum cos, sum sin
 
 struct RepState {
     double beta;
-    uint64_t t;              // sweeps completed
+    uint64_t t;              // sweeps completed (flips finalised)
+    uint64_t tl;             // the sweep whose links were activated and labelled last
     double dir[2][2];        // mirror direction of sweep t in slot t&1
     unsigned long long ties[2];  // near ties of sweep t in slot t&1
     uint64_t pad0;
@@ -110,8 +111,8 @@ struct RepState {
 //            a root's parent is itself.  Node id = tile * NB + slot.
 //   cross    per tile two words: active links over the right edge (bit y) and
 //            over the bottom edge (bit x)
-//   scoin    per tile four words (one buffer): bit s = flip coin of the cluster
-//            of used slot s, drawn between the merge and the flip
+//   ecoin    per tile four words (one buffer): bit p = flip coin of the cluster
+//            at edge position p, drawn between the merge and the flip
 constexpr uint32_t kBoundary = 0x8000u;
 
 struct RepDesc {
@@ -121,7 +122,7 @@ struct RepDesc {
     uint8_t *bslot[2];       // edge positions -> slot
     unsigned long long *node[2];  // boundary-component forest
     unsigned long long *cross[2]; // links over the right / bottom tile edges
-    unsigned long long *scoin;    // per tile 4 words: flip coin of every used edge slot
+    unsigned long long *ecoin;    // per tile 4 words: flip coin of the cluster at every edge position
     float2 *edge[2];         // spins before sweep t in slot t&1: per tile, its first column (TH) then first row (TW)
     double *partials;        // kNumSums planes of per-tile sums: partials[k * ntiles + tile]
     RepState *st;

@@ -292,7 +292,7 @@ int xy_group_round(xy_group *g, int64_t max_sweeps, int64_t *ran)
     fa.dbeta_min = g->pcc.dbeta_min;
     fa.halve_every = g->pcc.halve_every;
     fa.target = g->pcc.target;
-    bool ready = false;
+    Pipe pp;
     auto plain = [](int, auto launch) { return launch(); };
     for (int64_t j = 0; j < k; ++j) {
         // the next sweep's links may be activated in this pass only if no
@@ -300,7 +300,7 @@ int xy_group_round(xy_group *g, int64_t max_sweeps, int64_t *ran)
         bool fuse = j + 1 < k;
         for (int32_t s : g->order)
             if ((g->slots[s].done + j + 1) % g->pcc.window == 0) fuse = false;
-        GCHECK(g, enqueue_sweep_lc(g->lc, g->d_reps, n, fa, fuse, &ready, g->stream, plain));
+        GCHECK(g, enqueue_sweep_lc(g->lc, g->d_reps, n, fa, fuse, pp, g->stream, plain));
     }
     GCHECK(g, hipStreamSynchronize(g->stream));
     for (int32_t s : g->order) {

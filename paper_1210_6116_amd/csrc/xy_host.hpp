@@ -30,7 +30,7 @@ struct Resolved {
 
 // Per-replica byte layout inside an arena.
 struct RepLayout {
-    size_t c, s, lab[2], bx[2], by[2], bslot[2], node[2], cross[2], edge[2], scoin, partials, end;
+    size_t c, s, lab[2], bx[2], by[2], bslot[2], node[2], cross[2], edge[2], ecoin, partials, end;
 };
 
 struct Plan {
@@ -47,32 +47,46 @@ int make_plan(const xy_params *p, int32_t n, Plan &P);
 // Descriptor of replica k of plan P whose buffers start at base (layout P.lay[k]).
 void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *base, xy::RepState *st, int64_t tile_base,
                int32_t idx, xy::RepDesc &d);
-// One sweep of every replica in lc: links + tile labels (unless *ready), merge
-// of the boundary components, flip (fused with the next sweep's links when
-// fuse_next), finalize.  kind_timer(kind, launch) runs each
-// launch (and may bracket it with events).
+// Launch state carried from one sweep to the next inside a sequence.
+struct Pipe {
+    bool ready = false;        // the links of the next sweep are activated and labelled
+    bool fin_pending = false;  // the last flip's finalisation is still to run
+    xy::FlipArgs fa_pending;   // its arguments
+};
+
+// One sweep of every replica in lc: links + tile labels (unless pp.ready),
+// merge of the boundary components, edge coins (with the deferred
+// finalisation of the previous sweep), then either the flip and its
+// finalisation, or (fuse_next) the flip fused with the next sweep's links,
+// whose finalisation runs with the next sweep's edge coins.  A sequence must
+// end with fuse_next = false.  timer(kind, launch) runs each launch (and may
+// bracket it with events).
 template <typename Timer>
 hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int32_t nrep, const xy::FlipArgs &fa,
-                            bool fuse_next, bool *ready, hipStream_t s, Timer &&timer)
+                            bool fuse_next, Pipe &pp, hipStream_t s, Timer &&timer)
 {
     hipError_t e = hipSuccess;
-    if (!*ready) {
+    if (!pp.ready) {
         e = timer(XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, s); });
         if (e != hipSuccess) return e;
     }
     e = timer(XY_K_MERGE, [&] {
         const hipError_t e2 = xy::launch_merge(lc, true, s);
-        return e2 == hipSuccess ? xy::launch_resolve(lc, s) : e2;
+        return e2 == hipSuccess ? xy::launch_resolve(lc, pp.fin_pending ? &pp.fa_pending : nullptr, s) : e2;
     });
     if (e != hipSuccess) return e;
-    const bool fuse = fuse_next;
-    if (fuse)
+    pp.fin_pending = false;
+    if (fuse_next) {
         e = timer(XY_K_FUSED, [&] { return xy::launch_tile(lc, xy::TILE_FUSED, s); });
-    else
-        e = timer(XY_K_FLIP, [&] { return xy::launch_tile(lc, xy::TILE_FLIP, s); });
+        pp.ready = true;
+        pp.fin_pending = true;
+        pp.fa_pending = fa;
+        return e;
+    }
+    e = timer(XY_K_FLIP, [&] { return xy::launch_tile(lc, xy::TILE_FLIP, s); });
     if (e != hipSuccess) return e;
     e = timer(XY_K_FINALIZE, [&] { return xy::launch_finalize(d_reps, nrep, fa, nullptr, s); });
-    *ready = fuse;
+    pp.ready = false;
     return e;
 }
 

@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "xy_device.hpp"
 #include "xy_launch.hpp"
@@ -346,12 +347,27 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int B = FIXED ? BT : band_rows(TH), yb = wave * B;
     XY_G RepState *st = gmem(R.st);
+    // site (yb + k, lane) belongs to this tile (always, for fixed tiles)
+    auto own = [&](int k) -> bool { return FIXED || (yb + k < TH && lane < TW); };
+    XY_G float *__restrict__ cp = gmem(R.c);
+    XY_G float *__restrict__ sp = gmem(R.s);
+    // the wave's own spins first: their addresses do not depend on the sweep
+    // counter, so these loads overlap its read
+    float c0[BMAX], s0[BMAX];
+    if constexpr (MODE != M_PLANES) {
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (own(k)) {
+                const IT i = T.site(yb + k, lane);
+                c0[k] = cp[i];
+                s0[k] = sp[i];
+            }
+        }
+    }
     const uint64_t t = st->t;
     const int par = (int)(t & 1);
     const uint64_t tb = MODE == M_FUSED ? t + 1 : t;  // sweep whose links this launch activates
     const int pb = (int)(tb & 1);
-    // site (yb + k, lane) belongs to this tile (always, for fixed tiles)
-    auto own = [&](int k) -> bool { return FIXED || (yb + k < TH && lane < TW); };
 
     float2 *spin = (float2 *)smem;
     uint64_t *bxm = (uint64_t *)(spin + (TH + 1) * SS);
@@ -360,17 +376,13 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     uint64_t *rcoin = scoin + 4; // 64 words: coins of the tile's rows
     uint32_t *lab_s = (uint32_t *)(rcoin + 64);
     const int64_t ecount = TH + TW;
-    XY_G float *__restrict__ cp = gmem(R.c);
-    XY_G float *__restrict__ sp = gmem(R.s);
 
     if constexpr (FLIP) {
         const XY_G uint16_t *__restrict__ lab = gmem(R.lab[par]);
-        const XY_G uint8_t *__restrict__ bsl = gmem(R.bslot[par]);
         const XY_G float2 *__restrict__ eg = gmem(R.edge[par]);
         const double rx = st->dir[par][0], ry = st->dir[par][1];
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
         const uint32_t tf = (uint32_t)t;
-        const int NB = R.nb;
         auto flip_one = [&](bool f, float c0, float s0, float &c1, float &s1) -> bool {
             double c = c0, s = s0;
             if (f) {
@@ -387,43 +399,36 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
             s1 = (float)s;
             return f || renorm;
         };
-        // all independent loads of the wave's rows first: labels and spins
+        // labels of the wave's rows
         uint32_t lv[BMAX];
-        float c0[BMAX], s0[BMAX];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            if (own(k)) {
-                const IT i = T.site(yb + k, lane);
-                lv[k] = lab[i];
-                c0[k] = cp[i];
-                s0[k] = sp[i];
-            }
-        }
+        for (int k = 0; k < B; ++k)
+            if (own(k)) lv[k] = lab[T.site(yb + k, lane)];
         // halo: right column and bottom row of the neighbouring tiles (spins
-        // before the sweep from their edge copies, coins from their edge slots
-        // and slot coins), flipped here exactly as their owners flip them
-        const XY_G unsigned long long *__restrict__ sc = gmem(R.scoin);
+        // before the sweep from their edge copies, coins from their edge-position
+        // coins), flipped here exactly as their owners flip them
+        const XY_G unsigned long long *__restrict__ ec = gmem(R.ecoin);
         float2 he = make_float2(0.f, 0.f);
         int hslot = -1;
         bool hcoin = false;
         if (wave == 0 && lane < TH) {
             const int64_t nt = T.right_tile();
-            const uint32_t sl = bsl[nt * NB + 2 * TW + lane];
-            hcoin = (sc[nt * 4 + (sl >> 6)] >> (sl & 63u)) & 1ull;
+            const int q = 2 * TW + lane;  // the neighbour's left column
+            hcoin = (ec[nt * 4 + (q >> 6)] >> (q & 63)) & 1ull;
             he = ldf2(eg + nt * ecount + lane);
             hslot = lane * SS + TW;
         } else if (wave == 1 && lane < TW) {
             const int64_t nt = T.down_tile();
-            const uint32_t sl = bsl[nt * NB + lane];
-            hcoin = (sc[nt * 4 + (sl >> 6)] >> (sl & 63u)) & 1ull;
+            hcoin = (ec[nt * 4] >> lane) & 1ull;  // the neighbour's top row
             he = ldf2(eg + nt * ecount + TH + lane);
             hslot = TH * SS + lane;
         }
-        // coins of the clusters that reach the tile's edge (bit s of scoin: the
-        // slot coins drawn after the merge), and of clusters inside the tile
-        // (rooted at one of its sites): the Philox block holding a row's
+        // coins of the clusters that reach the tile's edge (bit p of scoin: the
+        // coin of edge position p, drawn after the merge; a boundary label
+        // names its slot, itself an edge position), and of clusters inside the
+        // tile (rooted at one of its sites): the Philox block holding a row's
         // sites, bit x of rcoin[y] for site (y, x)
-        if (threadIdx.x < 4) scoin[threadIdx.x] = sc[lt * 4 + threadIdx.x];
+        if (threadIdx.x < 4) scoin[threadIdx.x] = ec[lt * 4 + threadIdx.x];
         if (threadIdx.x >= 64 && threadIdx.x < 64 + TH) {
             const int y = threadIdx.x - 64;
             const IT site0 = T.site(y, 0);
@@ -464,15 +469,6 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
             stf2(en + TH + lane, spin[lane]);
     } else if constexpr (MODE == M_BONDS) {
         // spins before the sweep: own sites from the planes, halo from edge copies
-        float c0[BMAX], s0[BMAX];
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-            if (own(k)) {
-                const IT i = T.site(yb + k, lane);
-                c0[k] = cp[i];
-                s0[k] = sp[i];
-            }
-        }
         const XY_G float2 *__restrict__ eg = gmem(R.edge[par]);
         if (wave == 0 && lane < TW)
             spin[TH * SS + lane] = ldf2(eg + T.down_tile() * ecount + TH + lane);
@@ -604,6 +600,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     }
 
     // ---- in-tile labelling of sweep tb
+    if (lt == 0 && threadIdx.x == 0) st->tl = tb;
     const uint64_t twmask = TW == 64 ? ~0ull : ((1ull << (TW & 63)) - 1ull);
     const uint64_t inner = twmask >> 1;  // link x -> x+1 stays inside the tile
     const uint64_t below = (1ull << lane) - 1ull;
@@ -711,7 +708,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
 // ------------------------------------------------- merge across tiles
 // One wave per tile edge (0: right, TH links; 1: bottom, TW links).  Every
 // active link over the edge unites the boundary nodes of its two end
-// components; a link whose pair equals the previous lane's is skipped.  Reads
+// components, once per distinct pair of nodes in the wave.  Reads
 // are contiguous (the edge's link mask and the two rows of edge slots); the
 // unions touch only the forest of boundary nodes.
 __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ reps,
@@ -726,7 +723,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
     const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
-    const uint64_t t = gmem(R.st)->t;
+    const uint64_t t = gmem(R.st)->tl;  // the sweep whose links were labelled last
     const int par = (int)(t & 1);
     const int NB = R.nb;
     const uint64_t m = gmem(R.cross[par])[2 * lt + edge];
@@ -740,45 +737,71 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
         a = (uint32_t)(lt * NB) + bsl[lt * NB + pa];
         b = (uint32_t)(nt * NB) + bsl[nt * NB + pn];
     }
-    const uint32_t pa = __shfl_up(a, 1), pbv = __shfl_up(b, 1);
-    const int pon = __shfl_up((int)on, 1);
-    const bool dup = lane > 0 && pon && pa == a && pbv == b;
-    if (on && !dup) union_nodes(gmem(R.node[par]), a, b);
+    // one union per distinct pair of the wave: the lowest lane holding a pair
+    // not seen yet leads it, and every lane with the same pair drops out
+    uint64_t todo = __ballot(on && a != b);
+    bool lead = false;
+    while (todo) {
+        const int l = __ffsll((long long)todo) - 1;
+        const uint32_t la = __shfl(a, l), lb = __shfl(b, l);
+        lead = lead || lane == l;
+        todo &= ~__ballot(on && a == la && b == lb);
+    }
+    if (lead) union_nodes(gmem(R.node[par]), a, b);
     if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
 }
 
-// ------------------------------------------------- coins of edge slots
+// ------------------------------------------------- coins of edge positions
 // After the merge: every used slot (the smallest edge position of its tile
 // component) finds the smallest site of its cluster and draws that cluster's
-// flip coin; bit s of scoin[4 * tile + s / 64] is the coin of slot s.  One
-// block per tile, one thread per edge position.
+// flip coin; then every edge position takes the coin of its slot.  Bit p of
+// ecoin[4 * tile + p / 64] is the coin of the cluster at edge position p (a
+// boundary label's slot is itself an edge position).  One block per tile, one
+// thread per edge position.
+template <int NT>
+__device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red);
+
 __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict__ reps,
                                                        const uint32_t *__restrict__ tile_rep, int32_t nrep,
-                                                       int64_t gtile0)
+                                                       int64_t gtile0, int64_t ntile, int32_t fin, FlipArgs fa)
 {
+    __shared__ uint64_t sc[kWaves];
+    __shared__ double red[kWaves * kNumSums];
+    if (blockIdx.x >= ntile) {
+        // deferred finalisation of the previous sweep (its flip was fused)
+        if (fin) finalize_rep<kThreads>(reps[blockIdx.x - ntile], fa, nullptr, red);
+        return;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
-    const uint64_t t = gmem(R.st)->t;
+    const uint64_t t = gmem(R.st)->tl;
     const int par = (int)(t & 1);
     const int NB = R.nb;
     const int p = threadIdx.x;
+    uint32_t sl = 0;
     bool cb = false;
-    if (p < NB && gmem(R.bslot[par])[lt * NB + p] == (uint8_t)p)
-        cb = coin_of(R, (uint32_t)t, root_key(gmem(R.node[par]), (uint32_t)(lt * NB + p)));
+    if (p < NB) {
+        sl = gmem(R.bslot[par])[lt * NB + p];
+        if (sl == (uint32_t)p) cb = coin_of(R, (uint32_t)t, root_key(gmem(R.node[par]), (uint32_t)(lt * NB + p)));
+    }
     const uint64_t m = __ballot(cb);
-    if (lane == 0) gmem(R.scoin)[lt * 4 + wave] = m;
+    if (lane == 0) sc[wave] = m;
+    __syncthreads();
+    const bool pc = p < NB && ((sc[sl >> 6] >> (sl & 63u)) & 1ull);
+    const uint64_t m2 = __ballot(pc);
+    if (lane == 0) gmem(R.ecoin)[lt * 4 + wave] = m2;
 }
 
 // ------------------------------------------------- finalise a sweep
 // One block per replica: the per-tile sums in a fixed order, the observables,
 // the PCC window / beta step, and the sweep counter.  measure_out != null:
 // observables of the current configuration only (no counters touched).
-__global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restrict__ reps, FlipArgs fa,
-                                                           xy_obs *measure_out)
+// Besides its own kernel, it runs in extra blocks of the edge-coin kernel of
+// the next sweep when the flip was fused with that sweep's links.
+template <int NT>
+__device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red)
 {
-    __shared__ double red[(kFinThreads / 64) * kNumSums];
-    const RepDesc &R = reps[blockIdx.x];
     RepState *st = R.st;
     double tot[kNumSums];
 #pragma unroll
@@ -786,22 +809,22 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restr
     const int64_t nt = R.ntiles;
     // four tiles per thread per round, their loads issued together
     int64_t j = threadIdx.x;
-    for (; j + 3 * kFinThreads < nt; j += 4 * kFinThreads) {
+    for (; j + 3 * NT < nt; j += 4 * NT) {
         double x[4][kNumSums];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int k = 0; k < kNumSums; ++k) x[q][k] = gmem(R.partials)[k * nt + j + q * kFinThreads];
+            for (int k = 0; k < kNumSums; ++k) x[q][k] = gmem(R.partials)[k * nt + j + q * NT];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int k = 0; k < kNumSums; ++k) tot[k] += x[q][k];
     }
-    for (; j < nt; j += kFinThreads) {
+    for (; j < nt; j += NT) {
 #pragma unroll
         for (int k = 0; k < kNumSums; ++k) tot[k] += gmem(R.partials)[k * nt + j];
     }
-    block_sum<kNumSums, kFinThreads / 64>(tot, red);
+    block_sum<kNumSums, NT / 64>(tot, red);
     if (threadIdx.x != 0) return;
 
     const uint64_t t = st->t;
@@ -868,6 +891,13 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restr
         }
     }
     st->t = t + 1;
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restrict__ reps, FlipArgs fa,
+                                                           xy_obs *measure_out)
+{
+    __shared__ double red[(kFinThreads / 64) * kNumSums];
+    finalize_rep<kFinThreads>(reps[blockIdx.x], fa, measure_out, red);
 }
 
 // ------------------------------------------------- measure (no update)
@@ -1012,10 +1042,14 @@ hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const Launch &lc, hipStream_t s)
+hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(lc.gtile_end - lc.gtile0)), dim3(kThreads), 0, s, lc.reps,
-                       lc.tile_rep, lc.nrep, lc.gtile0);
+    const int64_t ntile = lc.gtile_end - lc.gtile0;
+    FlipArgs fa;
+    if (fin) fa = *fin;
+    else std::memset(&fa, 0, sizeof fa);
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(ntile + (fin ? lc.nrep : 0))), dim3(kThreads), 0, s, lc.reps,
+                       lc.tile_rep, lc.nrep, lc.gtile0, ntile, (int32_t)(fin != nullptr), fa);
     return hipGetLastError();
 }
 
