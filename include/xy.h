@@ -196,12 +196,13 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
  * also copied out and *nsamples receives how many. */
 enum {
     XY_K_BONDS = 0,    /* link activation + in-tile labelling */
-    XY_K_MERGE = 1,    /* union across tile edges */
-    XY_K_FLIP = 2,     /* root lookup, reflection, sums */
+    XY_K_MERGE = 1,    /* union of boundary components across tile edges (+ a deferred finalisation) */
+    XY_K_FLIP = 2,     /* cluster coins, reflection, sums */
     XY_K_FUSED = 3,    /* flip of sweep t + links and tile labels of sweep t+1 */
     XY_K_FINALIZE = 4, /* observables, PCC step, counters */
-    XY_K_SWEEP = 5,
-    XY_K_COUNT = 6
+    XY_K_COINS = 5,    /* coins of the clusters at tile edges */
+    XY_K_SWEEP = 6,
+    XY_K_COUNT = 7
 };
 int xy_timing(xy_handle *h, int32_t enable);
 int xy_timing_read(xy_handle *h, double *ms, int64_t *launches, double *samples, int64_t cap,

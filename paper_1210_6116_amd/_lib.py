@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxy.so")
 
 XY_OK, XY_EINVAL, XY_ENOMEM, XY_EDEVICE, XY_ESTATE, XY_EBUDGET = 0, -1, -2, -3, -4, -5
 XY_START_HOT, XY_START_COLD = 0, 1
-XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_FINALIZE, XY_K_SWEEP, XY_K_COUNT = 0, 1, 2, 3, 4, 5, 6
-KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize", "sweep")
+XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_FINALIZE, XY_K_COINS, XY_K_SWEEP, XY_K_COUNT = range(8)
+KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize", "coins", "sweep")
 
 
 class XYError(RuntimeError):

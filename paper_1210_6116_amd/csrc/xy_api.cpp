@@ -758,7 +758,7 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     lc.gtile0 = 0;
     lc.gtile_end = r.ntiles;
     if (e == hipSuccess) e = xy::launch_tile(lc, xy::TILE_PLANES, s);
-    if (e == hipSuccess) e = xy::launch_merge(lc, false, s);
+    if (e == hipSuccess) e = xy::launch_merge(lc, false, nullptr, s);
     if (e == hipSuccess) e = xy::launch_flatten(d_rep, 0, 0, r.N, P.big_index, d_labels, label_bits, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(mem);

@@ -55,8 +55,8 @@ struct Pipe {
 };
 
 // One sweep of every replica in lc: links + tile labels (unless pp.ready),
-// merge of the boundary components, edge coins (with the deferred
-// finalisation of the previous sweep), then either the flip and its
+// merge of the boundary components (with the deferred finalisation of the
+// previous sweep), edge coins, then either the flip and its
 // finalisation, or (fuse_next) the flip fused with the next sweep's links,
 // whose finalisation runs with the next sweep's edge coins.  A sequence must
 // end with fuse_next = false.  timer(kind, launch) runs each launch (and may
@@ -70,10 +70,9 @@ hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int
         e = timer(XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, s); });
         if (e != hipSuccess) return e;
     }
-    e = timer(XY_K_MERGE, [&] {
-        const hipError_t e2 = xy::launch_merge(lc, true, s);
-        return e2 == hipSuccess ? xy::launch_resolve(lc, pp.fin_pending ? &pp.fa_pending : nullptr, s) : e2;
-    });
+    e = timer(XY_K_MERGE, [&] { return xy::launch_merge(lc, true, pp.fin_pending ? &pp.fa_pending : nullptr, s); });
+    if (e != hipSuccess) return e;
+    e = timer(XY_K_COINS, [&] { return xy::launch_resolve(lc, s); });
     if (e != hipSuccess) return e;
     pp.fin_pending = false;
     if (fuse_next) {

@@ -175,24 +175,45 @@ __device__ void union_lds(uint32_t *lab, uint32_t a, uint32_t b)
 // key is never larger than its child's, so a root carries the smallest key,
 // i.e. the smallest site, of everything united under it.
 
-// Root entry of node n, with intermediate pointer jumping: every node on the
-// path is re-pointed at its grandparent.  An entry only ever moves to an
-// ancestor in the same set and roots are never overwritten, so these plain
-// stores are benign while other threads hook roots; a hook such a store may
-// undo is always followed by the union of the hooked root's former parent.
-__device__ unsigned long long find_jump(XY_G unsigned long long *P, uint32_t n)
+// Root entries of nodes a and b, the two paths walked in step (their loads
+// overlap), with intermediate pointer jumping: every node on a path is
+// re-pointed at its grandparent.  An entry only ever moves to an ancestor in
+// the same set and roots are never overwritten, so these plain stores are
+// benign while other threads hook roots; a hook such a store may undo is
+// always followed by the union of the hooked root's former parent.
+__device__ void find_pair(XY_G unsigned long long *P, uint32_t a, uint32_t b, unsigned long long &ra,
+                          unsigned long long &rb)
 {
-    unsigned long long e = P[n];
-    if ((uint32_t)e == n) return e;
-    uint32_t prev = n;
-    while (true) {
-        const uint32_t par = (uint32_t)e;
-        const unsigned long long g = P[par];
-        if ((uint32_t)g == par) return g;
-        P[prev] = g;
-        prev = par;
-        e = g;
+    unsigned long long ea = P[a], eb = P[b];
+    uint32_t pa = a, pb = b;  // the nodes whose entries ea, eb are
+    bool da = (uint32_t)ea == a, db = (uint32_t)eb == b;
+    while (!(da && db)) {
+        unsigned long long ga = 0, gb = 0;
+        if (!da) ga = P[(uint32_t)ea];
+        if (!db) gb = P[(uint32_t)eb];
+        if (!da) {
+            const uint32_t par = (uint32_t)ea;
+            if ((uint32_t)ga == par) {
+                da = true;
+            } else {
+                P[pa] = ga;
+                pa = par;
+            }
+            ea = ga;
+        }
+        if (!db) {
+            const uint32_t par = (uint32_t)eb;
+            if ((uint32_t)gb == par) {
+                db = true;
+            } else {
+                P[pb] = gb;
+                pb = par;
+            }
+            eb = gb;
+        }
     }
+    ra = ea;
+    rb = eb;
 }
 
 // Lock-free union: the root with the larger key is hooked under the other
@@ -201,7 +222,8 @@ __device__ unsigned long long find_jump(XY_G unsigned long long *P, uint32_t n)
 __device__ void union_nodes(XY_G unsigned long long *P, uint32_t a, uint32_t b)
 {
     while (true) {
-        unsigned long long ra = find_jump(P, a), rb = find_jump(P, b);
+        unsigned long long ra, rb;
+        find_pair(P, a, b, ra, rb);
         if (ra == rb) return;
         if (ra > rb) {
             const unsigned long long tmp = ra;
@@ -711,10 +733,21 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
 // components, once per distinct pair of nodes in the wave.  Reads
 // are contiguous (the edge's link mask and the two rows of edge slots); the
 // unions touch only the forest of boundary nodes.
+template <int NT>
+__device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red);
+
 __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ reps,
                                                      const uint32_t *__restrict__ tile_rep, int32_t nrep,
-                                                     int64_t gtile0, int64_t gtile_end, int32_t next_dir)
+                                                     int64_t gtile0, int64_t gtile_end, int32_t next_dir,
+                                                     int64_t nblk, int32_t fin, FlipArgs fa)
 {
+    if (blockIdx.x >= nblk) {
+        // deferred finalisation of the previous sweep (its flip was fused):
+        // one extra block per replica, concurrent with the unions
+        __shared__ double red[kWaves * kNumSums];
+        if (fin) finalize_rep<kThreads>(reps[blockIdx.x - nblk], fa, nullptr, red);
+        return;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
     const int64_t gtile = gtile0 + (gw >> 1);
@@ -726,10 +759,9 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
     const uint64_t t = gmem(R.st)->tl;  // the sweep whose links were labelled last
     const int par = (int)(t & 1);
     const int NB = R.nb;
-    const uint64_t m = gmem(R.cross[par])[2 * lt + edge];
-    const bool on = lane < (edge ? T.TW : T.TH) && ((m >> lane) & 1ull);
+    const int nlinks = edge ? T.TW : T.TH;
     uint32_t a = 0, b = 0;
-    if (on) {
+    if (lane < nlinks) {  // read with the link mask, not after it
         const XY_G uint8_t *bsl = gmem(R.bslot[par]);
         const int64_t nt = edge ? T.down_tile() : T.right_tile();
         const int pa = edge ? T.TW + lane : 2 * T.TW + T.TH + lane;  // own bottom row / right column
@@ -737,6 +769,8 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
         a = (uint32_t)(lt * NB) + bsl[lt * NB + pa];
         b = (uint32_t)(nt * NB) + bsl[nt * NB + pn];
     }
+    const uint64_t m = gmem(R.cross[par])[2 * lt + edge];
+    const bool on = lane < nlinks && ((m >> lane) & 1ull);
     // one union per distinct pair of the wave: the lowest lane holding a pair
     // not seen yet leads it, and every lane with the same pair drops out
     uint64_t todo = __ballot(on && a != b);
@@ -758,20 +792,11 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
 // ecoin[4 * tile + p / 64] is the coin of the cluster at edge position p (a
 // boundary label's slot is itself an edge position).  One block per tile, one
 // thread per edge position.
-template <int NT>
-__device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red);
-
 __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict__ reps,
                                                        const uint32_t *__restrict__ tile_rep, int32_t nrep,
-                                                       int64_t gtile0, int64_t ntile, int32_t fin, FlipArgs fa)
+                                                       int64_t gtile0)
 {
     __shared__ uint64_t sc[kWaves];
-    __shared__ double red[kWaves * kNumSums];
-    if (blockIdx.x >= ntile) {
-        // deferred finalisation of the previous sweep (its flip was fused)
-        if (fin) finalize_rep<kThreads>(reps[blockIdx.x - ntile], fa, nullptr, red);
-        return;
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
@@ -797,8 +822,8 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
 // One block per replica: the per-tile sums in a fixed order, the observables,
 // the PCC window / beta step, and the sweep counter.  measure_out != null:
 // observables of the current configuration only (no counters touched).
-// Besides its own kernel, it runs in extra blocks of the edge-coin kernel of
-// the next sweep when the flip was fused with that sweep's links.
+// Besides its own kernel, it runs in extra blocks of the merge kernel of the
+// next sweep when the flip was fused with that sweep's links.
 template <int NT>
 __device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red)
 {
@@ -1033,23 +1058,23 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const Launch &lc, bool next_dir, hipStream_t s)
+hipError_t launch_merge(const Launch &lc, bool next_dir, const FlipArgs *fin, hipStream_t s)
 {
     const int64_t waves = 2 * (lc.gtile_end - lc.gtile0);
-    const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves)), block(kThreads);
-    hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end,
-                       (int32_t)next_dir);
-    return hipGetLastError();
-}
-
-hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s)
-{
-    const int64_t ntile = lc.gtile_end - lc.gtile0;
+    const int64_t nblk = (waves + kWaves - 1) / kWaves;
     FlipArgs fa;
     if (fin) fa = *fin;
     else std::memset(&fa, 0, sizeof fa);
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(ntile + (fin ? lc.nrep : 0))), dim3(kThreads), 0, s, lc.reps,
-                       lc.tile_rep, lc.nrep, lc.gtile0, ntile, (int32_t)(fin != nullptr), fa);
+    const dim3 grid((unsigned)(nblk + (fin ? lc.nrep : 0))), block(kThreads);
+    hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end,
+                       (int32_t)next_dir, nblk, (int32_t)(fin != nullptr), fa);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(const Launch &lc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(lc.gtile_end - lc.gtile0)), dim3(kThreads), 0, s, lc.reps,
+                       lc.tile_rep, lc.nrep, lc.gtile0);
     return hipGetLastError();
 }
 
