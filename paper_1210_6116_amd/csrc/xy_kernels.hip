@@ -283,6 +283,35 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *red /* NW*K */
     }
 }
 
+// First half of block_sum: each wave's sums into red[wave * K + k]; a later
+// barrier and fold_sums finish it (the tile kernel reuses a barrier it needs
+// anyway).
+template <int K>
+__device__ __forceinline__ void wave_sums(double (&v)[K], double *red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    }
+}
+
+template <int K, int NW>
+__device__ __forceinline__ void fold_sums(double (&v)[K], const double *red)
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = red[k];
+        for (int w2 = 1; w2 < NW; ++w2) s += red[w2 * K + k];
+        v[k] = s;
+    }
+}
+
 __device__ __forceinline__ void store_partials(const RepDesc &R, int64_t lt, const double (&v)[kNumSums])
 {
     if (threadIdx.x == 0) {
@@ -572,8 +601,15 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         }
     }
     if constexpr (FLIP) {
-        block_sum<kNumSums, NW>(v, red);
-        store_partials(R, lt, v);
+        wave_sums<kNumSums>(v, red);
+        if constexpr (!CCL) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                fold_sums<kNumSums, NW>(v, red);
+                store_partials(R, lt, v);
+            }
+            return;
+        }
     }
     if constexpr (MODE == M_PLANES) {
         const XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
@@ -591,6 +627,16 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     if constexpr (!CCL) return;
 
     __syncthreads();
+    if constexpr (FLIP) {
+        if (threadIdx.x == 0) {
+            fold_sums<kNumSums, NW>(v, red);
+            store_partials(R, lt, v);
+        }
+    }
+    // smallest edge position per tile-local root, in the spin area (free now)
+    uint32_t *smin = (uint32_t *)smem;
+    const uint32_t NONE = 0xFFFFFFFFu;
+    for (int q = threadIdx.x; q < TW * TH; q += NT) smin[q] = NONE;
     if constexpr (BONDS) {
         // active-link bit planes of sweep tb
         XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
@@ -626,7 +672,6 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     const uint64_t twmask = TW == 64 ? ~0ull : ((1ull << (TW & 63)) - 1ull);
     const uint64_t inner = twmask >> 1;  // link x -> x+1 stays inside the tile
     const uint64_t below = (1ull << lane) - 1ull;
-    const uint32_t NONE = 0xFFFFFFFFu;
     // 1) each wave scans its band of rows top-down.  A run of x-links takes
     //    the smallest label among the runs above that it touches through a
     //    y-link (segmented prefix minimum over the run's lanes, then read at
@@ -654,9 +699,13 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         const uint32_t low = 0xFFFFu - (pm & 0xFFFFu);
         const uint32_t m = low == 0xFFFFu ? NONE : low;
         const uint32_t lab = m != NONE ? m : (uint32_t)(y * TW + start);
+        // a run's lanes below one run above share their candidate: only the
+        // first of them records its union
+        const uint32_t cleft = __shfl_up(cand, 1);
+        const bool again = lane > start && cleft == cand;
         if (act) {
             lab_s[y * TW + lane] = lab;
-            if (cand != NONE && cand != m) union_lds(lab_s, cand, m);
+            if (cand != NONE && cand != m && !again) union_lds(lab_s, cand, m);
         }
         lprev = lab;
     }
@@ -674,31 +723,22 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         }
     }
     __syncthreads();
-    // 3) tile-local roots; every site's entry is then its root
+    // 3) tile-local roots of the wave's sites, and of every edge position
+    //    (one thread each) with the smallest edge position per root: the
+    //    slot of a component that reaches the tile's edge
     uint32_t lr[BMAX];
 #pragma unroll
     for (int k = 0; k < B; ++k)
         if (own(k)) lr[k] = find_lds(lab_s, (uint32_t)((yb + k) * TW + lane));
-    __syncthreads();
-    uint32_t *smin = (uint32_t *)smem;  // smallest edge position per root (spin area, free now)
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-        if (own(k)) {
-            const uint32_t q = (uint32_t)((yb + k) * TW + lane);
-            lab_s[q] = lr[k];
-            if (lr[k] == q) smin[q] = NONE;
-        }
-    }
-    __syncthreads();
-    // 4) components reaching the tile's edge: slot = smallest edge position
     const int NB = R.nb;
-    const int p = threadIdx.x;  // NB <= 256 edge positions, one per thread
+    const int p = threadIdx.x;  // NB <= 256 edge positions
     uint32_t proot = 0;
     if (p < NB) {
-        proot = lab_s[T.edge_local(p)];
+        proot = find_lds(lab_s, (uint32_t)T.edge_local(p));
         atomicMin(&smin[proot], (uint32_t)p);
     }
     __syncthreads();
+    // 4) edge slots and boundary nodes of the tile
     if (p < NB) {
         const uint32_t sl = smin[proot];
         const int64_t nbase = lt * NB;
