@@ -370,8 +370,8 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
 // ----------------------------------------------------------- the tile kernel
 // LDS: spin[(TH+1)*(TW+1)] float2 (tile + right halo column + bottom halo row;
 //        reused for the smallest edge position of every tile-local root)
-//      | bxm[64], bym[64] u64 row masks of active links
-//      | scoin[4], rcoin[64] u64 flip coins of edge slots and of rows
+//      | bxm[TH], bym[TH] u64 row masks of active links
+//      | scoin[4], rcoin[TH] u64 flip coins of edge positions and of rows
 //      | lab[TW*TH] u32 tile-local union-find (labelling)
 // BT = rows per wave known at compile time (tiles of 64 x NW*BT for NW waves;
 // every loop over a wave's rows is unrolled and its independent loads are
@@ -422,10 +422,10 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
 
     float2 *spin = (float2 *)smem;
     uint64_t *bxm = (uint64_t *)(spin + (TH + 1) * SS);
-    uint64_t *bym = bxm + 64;
-    uint64_t *scoin = bym + 64;  // 4 words: coins of the edge slots
-    uint64_t *rcoin = scoin + 4; // 64 words: coins of the tile's rows
-    uint32_t *lab_s = (uint32_t *)(rcoin + 64);
+    uint64_t *bym = bxm + TH;
+    uint64_t *scoin = bym + TH;  // 4 words: coins of the edge positions
+    uint64_t *rcoin = scoin + 4; // TH words: coins of the tile's rows
+    uint32_t *lab_s = (uint32_t *)(rcoin + TH);
     const int64_t ecount = TH + TW;
 
     if constexpr (FLIP) {
@@ -1030,7 +1030,7 @@ __global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict_
 // ====================================================== host-side launchers
 size_t lds_bytes_tile(int TH)
 {
-    return (size_t)(TH + 1) * 65 * sizeof(float2) + (2 * 64 + 4 + 64) * sizeof(uint64_t) +
+    return (size_t)(TH + 1) * 65 * sizeof(float2) + (size_t)(3 * TH + 4) * sizeof(uint64_t) +
            (size_t)64 * TH * sizeof(uint32_t);
 }
 
