@@ -51,6 +51,21 @@ __device__ __forceinline__ void stf2(XY_G float2 *p, float2 v)
         ((unsigned long long)__float_as_uint(v.y) << 32) | (unsigned long long)__float_as_uint(v.x);
 }
 
+// Values that are the same in every lane (read from memory the kernel also
+// writes, so the compiler keeps them in vector registers) moved to scalar
+// registers, with everything derived from them.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    return __longlong_as_double((long long)uniform_u64((uint64_t)__double_as_longlong(v)));
+}
+
 struct U4 {
     uint32_t x, y, z, w;
 };
