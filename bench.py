@@ -206,7 +206,7 @@ def main():
     ap.add_argument("--L", type=int, default=4096)
     ap.add_argument("--beta", type=float, default=1.12)
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--cpu-sweeps", type=int, default=5)
+    ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
     ap.add_argument("--no-instrument", action="store_true", help="skip the instrumented pass")
     ap.add_argument("--no-extras", action="store_true",

@@ -32,7 +32,8 @@ _SOURCES = ("xy_oracle.c", "metropolis.c")
 _LIBNAME = "liboracle.so"
 _lib = None
 
-OBS_NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x")
+OBS_NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x", "mk2")
+NOBS = len(OBS_NAMES)
 PCC_TARGET = 0.636508  # critical beta*Upsilon with the periodic-boundary winding correction
 
 
@@ -201,10 +202,10 @@ def flip(L, lab, c, s, r, seed, rep, t, storage32=True):
 
 
 def measure(L, c, s, beta) -> np.ndarray:
-    """Observables (E, m2, ex, sx, ey, sy, ups_x) of one configuration."""
+    """Observables (E, m2, ex, sx, ey, sy, ups_x, mk2) of one configuration."""
     c = np.ascontiguousarray(c, dtype=np.float64)
     s = np.ascontiguousarray(s, dtype=np.float64)
-    obs = np.zeros(7)
+    obs = np.zeros(NOBS)
     _load().orc_measure(L, _ptr(c, ctypes.c_double), _ptr(s, ctypes.c_double), beta,
                         _ptr(obs, ctypes.c_double))
     return obs
@@ -237,7 +238,7 @@ class Lattice:
         bx = np.zeros(N, dtype=np.uint8)
         by = np.zeros(N, dtype=np.uint8)
         lab = np.zeros(N, dtype=np.int64)
-        obs = np.zeros(7)
+        obs = np.zeros(NOBS)
         ties = ctypes.c_int64(0)
         rc = _load().orc_sweep(self.L, _ptr(self.c, ctypes.c_double), _ptr(self.s, ctypes.c_double),
                                self.beta, self.seed, self.rep, self.t, int(self.storage32),
@@ -250,8 +251,8 @@ class Lattice:
         return obs, int(ties.value), bx, by, lab
 
     def run(self, n: int):
-        """n sweeps; returns (trace[n, 7], ties[n])."""
-        trace = np.zeros((n, 7))
+        """n sweeps; returns (trace[n, NOBS], ties[n])."""
+        trace = np.zeros((n, NOBS))
         ties = np.zeros(n, dtype=np.int64)
         rc = _load().orc_run(self.L, _ptr(self.c, ctypes.c_double), _ptr(self.s, ctypes.c_double),
                              self.beta, self.seed, self.rep, self.t, n, int(self.storage32),

@@ -283,10 +283,15 @@ void orc_renorm(int64_t L, double *c, double *s, int storage32)
 /*  obs[2] ex = sum_x cos / N     obs[3] sx = sum_x sin(th_i - th_j) / N     */
 /*  obs[4] ey, obs[5] sy (same over y-links)                                   */
 /*  obs[6] ups_x = ex - beta N sx^2 (sample of the helicity modulus)          */
-void orc_measure(int64_t L, const double *c, const double *s, double beta, double obs[7])
+/*  obs[7] mk2 = |sum_r s(r) e^{i k x}|^2 / N^2 at k = 2 pi / L along x: the   */
+/*         chi(k) of the second-moment correlation length, over N (as m2 is   */
+/*         chi(0) over N); |.|^2 sums the squared moduli of both components  */
+void orc_measure(int64_t L, const double *c, const double *s, double beta, double obs[8])
 {
     int64_t N = L * L;
+    const double pi = 3.14159265358979323846;
     double scx = 0, ssx = 0, scy = 0, ssy = 0, sc = 0, ss = 0;
+    double cre = 0, cim = 0, sre = 0, sim = 0; /* Fourier sums of cos and sin planes */
     for (int64_t i = 0; i < N; ++i) {
         int64_t j = right_of(i, L), k = down_of(i, L);
         scx += c[i] * c[j] + s[i] * s[j];
@@ -295,6 +300,11 @@ void orc_measure(int64_t L, const double *c, const double *s, double beta, doubl
         ssy += s[i] * c[k] - c[i] * s[k];
         sc += c[i];
         ss += s[i];
+        double kx = 2.0 * pi * (double)(i % L) / (double)L;
+        cre += c[i] * cos(kx);
+        cim += c[i] * sin(kx);
+        sre += s[i] * cos(kx);
+        sim += s[i] * sin(kx);
     }
     double n = (double)N;
     obs[0] = -(scx + scy) / n;
@@ -304,13 +314,14 @@ void orc_measure(int64_t L, const double *c, const double *s, double beta, doubl
     obs[4] = scy / n;
     obs[5] = ssy / n;
     obs[6] = obs[2] - beta * n * obs[3] * obs[3];
+    obs[7] = (cre * cre + cim * cim + sre * sre + sim * sim) / (n * n);
 }
 
 /* One Swendsen-Wang sweep t: direction, bonds, labels, flip, (renormalise), */
 /* measure.  Optional outputs (may be NULL): bx, by (N bytes each) and label */
 /* (N int64) of this sweep.  Returns 0, or -1 if memory ran out.             */
 int orc_sweep(int64_t L, double *c, double *s, double beta, uint64_t seed, uint32_t rep,
-              uint64_t t, int storage32, double obs[7], int64_t *ties, uint8_t *bx_out,
+              uint64_t t, int storage32, double obs[8], int64_t *ties, uint8_t *bx_out,
               uint8_t *by_out, int64_t *label_out)
 {
     int64_t N = L * L;
@@ -339,18 +350,18 @@ done:
     return rc;
 }
 
-/* n sweeps from sweep t0 at fixed beta; trace (n x 7, may be NULL) gets the */
+/* n sweeps from sweep t0 at fixed beta; trace (n x 8, may be NULL) gets the */
 /* observables after every sweep, ties (n, may be NULL) the near-tie counts. */
 int orc_run(int64_t L, double *c, double *s, double beta, uint64_t seed, uint32_t rep,
             uint64_t t0, int64_t n, int storage32, double *trace, int64_t *ties)
 {
     for (int64_t k = 0; k < n; ++k) {
-        double obs[7];
+        double obs[8];
         int64_t nt = 0;
         if (orc_sweep(L, c, s, beta, seed, rep, t0 + (uint64_t)k, storage32, obs, &nt, NULL,
                       NULL, NULL) != 0)
             return -1;
-        if (trace) memcpy(trace + 7 * k, obs, sizeof obs);
+        if (trace) memcpy(trace + 8 * k, obs, sizeof obs);
         if (ties) ties[k] = nt;
     }
     return 0;
@@ -373,7 +384,7 @@ int orc_pcc_run(int64_t L, double *c, double *s, double *beta, uint64_t seed, ui
     for (int64_t k = 0; k < nsteps; ++k) {
         double sum_ex = 0.0, sum_ns2 = 0.0;
         for (int64_t w = 0; w < window; ++w) {
-            double obs[7];
+            double obs[8];
             int64_t nt = 0;
             if (orc_sweep(L, c, s, *beta, seed, rep, t, storage32, obs, &nt, NULL, NULL, NULL) != 0)
                 return -1;

@@ -40,6 +40,12 @@ MUTANTS = [
     ("down_neighbour", "xy_oracle.c", "static int64_t down_of(int64_t i, int64_t L) { return ((i / L + 1) % L) * L + i % L; }",
      "static int64_t down_of(int64_t i, int64_t L) { return ((i / L + 1) % L) * L + (i + 1) % L; }",
      "test_oracle_physics.test_measure_matches_angle_formulas()"),
+    ("fourier_along_y", "xy_oracle.c", "double kx = 2.0 * pi * (double)(i % L) / (double)L;",
+     "double kx = 2.0 * pi * (double)(i / L) / (double)L;",
+     "test_oracle_physics.test_fourier_magnetisation_closed_forms()"),
+    ("fourier_drops_sin_part", "xy_oracle.c", "obs[7] = (cre * cre + cim * cim + sre * sre + sim * sim) / (n * n);",
+     "obs[7] = (cre * cre + sre * sre) / (n * n);",
+     "test_oracle_physics.test_measure_matches_angle_formulas()"),
     ("philox_key_bump", "xy_oracle.c", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE86u;",
      "test_oracle_philox.test_philox4x32_known_answers([0, 0, 0, 0], [0, 0], "
      "[0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8])"),

@@ -137,7 +137,25 @@ def test_measure_matches_angle_formulas():
             (np.cos(T).sum() ** 2 + np.sin(T).sum() ** 2) / N ** 2,
             np.cos(dx).sum() / N, np.sin(dx).sum() / N, np.cos(dy).sum() / N, np.sin(dy).sum() / N]
     want.append(want[2] - beta * N * want[3] ** 2)
+    # chi(k)/N at k = 2 pi / L along x, from a library FFT of each component
+    fc = np.fft.fft(np.cos(T), axis=1)[:, 1].sum()
+    fs = np.fft.fft(np.sin(T), axis=1)[:, 1].sum()
+    want.append((abs(fc) ** 2 + abs(fs) ** 2) / N ** 2)
     assert np.allclose(obs, want, atol=1e-13)
+
+
+def test_fourier_magnetisation_closed_forms():
+    # a spin wave of wave vector (2 pi / L, 0) has |sum s e^{ikx}|^2 = N^2 / 2
+    # and no magnetisation; a uniform state the reverse; a wave along y has
+    # no weight at k along x
+    L = 16
+    N = L * L
+    x = np.tile(np.arange(L), L)
+    y = np.repeat(np.arange(L), L)
+    for th, m2, mk2 in ((2 * np.pi * x / L, 0.0, 0.5), (np.full(N, 0.7), 1.0, 0.0),
+                        (2 * np.pi * y / L, 0.0, 0.0), (-2 * np.pi * x / L, 0.0, 0.5)):
+        obs = oracle.measure(L, np.cos(th), np.sin(th), 1.0)
+        assert abs(obs[OBS["m2"]] - m2) < 1e-13 and abs(obs[OBS["mk2"]] - mk2) < 1e-13
 
 
 @pytest.mark.parametrize("beta", [0.5, 1.12])
