@@ -78,6 +78,8 @@ typedef struct {
     double ex, sx;      /* sum over x-links of cos / sin(theta_i - theta_j), over N */
     double ey, sy;      /* the same over y-links */
     double ups_x;       /* ex - beta N sx^2 (sample of the helicity modulus) */
+    double mk2;         /* |sum_r s(r) exp(i k x)|^2 / N^2 at k = 2 pi / L: chi(k) / N of the
+                           second-moment correlation length (m2 is chi(0) / N) */
     uint64_t near_ties; /* bond decisions of the sweep with |u - p| < 1e-9 */
 } xy_obs;
 

@@ -37,7 +37,7 @@ class xy_obs(ctypes.Structure):
     _fields_ = [("sweep", ctypes.c_uint64), ("beta", ctypes.c_double), ("E", ctypes.c_double),
                 ("m2", ctypes.c_double), ("ex", ctypes.c_double), ("sx", ctypes.c_double),
                 ("ey", ctypes.c_double), ("sy", ctypes.c_double), ("ups_x", ctypes.c_double),
-                ("near_ties", ctypes.c_uint64)]
+                ("mk2", ctypes.c_double), ("near_ties", ctypes.c_uint64)]
 
 
 class xy_pcc(ctypes.Structure):
@@ -53,7 +53,7 @@ class xy_views(ctypes.Structure):
 
 OBS_DTYPE = np.dtype([("sweep", np.uint64), ("beta", np.float64), ("E", np.float64), ("m2", np.float64),
                       ("ex", np.float64), ("sx", np.float64), ("ey", np.float64), ("sy", np.float64),
-                      ("ups_x", np.float64), ("near_ties", np.uint64)])
+                      ("ups_x", np.float64), ("mk2", np.float64), ("near_ties", np.uint64)])
 assert OBS_DTYPE.itemsize == ctypes.sizeof(xy_obs)
 
 _lib = None

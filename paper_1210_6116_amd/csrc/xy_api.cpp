@@ -135,6 +135,10 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         off = align_up(off + (size_t)r.ntiles * 4 * sizeof(unsigned long long));
         l.partials = off;
         off = align_up(off + (size_t)r.ntiles * xy::kNumSums * sizeof(double));
+        l.partials2 = off;
+        off = align_up(off + (size_t)xy::kFinChunks * xy::kNumSums * sizeof(double));
+        l.fourier = off;
+        off = align_up(off + (size_t)r.L * 2 * sizeof(double));
         l.end = off;
     }
     P.off_reps = off;
@@ -168,6 +172,8 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
     }
     d.ecoin = reinterpret_cast<unsigned long long *>(A + l.ecoin);
     d.partials = reinterpret_cast<double *>(A + l.partials);
+    d.partials2 = reinterpret_cast<double *>(A + l.partials2);
+    d.fourier = reinterpret_cast<double *>(A + l.fourier);
     d.st = st;
     d.L = r.L;
     d.N = r.N;
@@ -421,6 +427,7 @@ int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_
                               hipMemcpyHostToDevice));
     for (int32_t k = 0; k < n; ++k) {
         HIPCHECK(h, xy::launch_init_spins(h->d_reps, k, P.res[k].N, p[k].start, h->stream));
+        HIPCHECK(h, xy::launch_init_fourier(h->d_reps, k, P.res[k].L, h->stream));
         HIPCHECK(h, xy::launch_edge_refresh(h->d_reps, k, P.res[k].ntiles, h->stream));
     }
     HIPCHECK(h, xy::launch_init_dir(h->d_reps, n, h->stream));
@@ -758,7 +765,7 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     lc.gtile0 = 0;
     lc.gtile_end = r.ntiles;
     if (e == hipSuccess) e = xy::launch_tile(lc, xy::TILE_PLANES, s);
-    if (e == hipSuccess) e = xy::launch_merge(lc, false, nullptr, s);
+    if (e == hipSuccess) e = xy::launch_merge(lc, false, false, s);
     if (e == hipSuccess) e = xy::launch_flatten(d_rep, 0, 0, r.N, P.big_index, d_labels, label_bits, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(mem);

@@ -96,7 +96,11 @@ __device__ __forceinline__ double unif64(uint32_t w) { return (double)w * (1.0 /
 // sweep) and RepState (mutated on the device: beta, sweep counter, direction,
 // PCC window, reduction counters).
 // ---------------------------------------------------------------------------
-constexpr int kNumSums = 6;  // Scx, Ssx, Scy, Ssy, sum cos, sum sin
+// Scx, Ssx, Scy, Ssy, sum cos, sum sin, then the Fourier sums at k = 2 pi / L
+// along x: sum cos e^{ikx} (real, imaginary), sum sin e^{ikx} (real, imaginary)
+constexpr int kNumSums = 10;
+constexpr int kLinkSums = 6;  // the first six
+constexpr int kFinChunks = 8; // chunks of the two-stage (deferred) finalisation
 
 struct RepState {
     double beta;
@@ -105,7 +109,7 @@ struct RepState {
     double dir[2][2];        // mirror direction of sweep t in slot t&1
     unsigned long long ties[2];  // near ties of sweep t in slot t&1
     uint64_t pad0;
-    double acc[8];           // PCC window sums: E, m2, ex, sx, ey, sy, ups_x, N sx^2
+    double acc[9];           // PCC window sums: E, m2, ex, sx, ey, sy, ups_x, N sx^2, mk2
     int64_t acc_n;           // sweeps in the running window
     int64_t pcc_k;           // PCC steps taken (halving schedule)
     uint64_t ties_total;
@@ -140,6 +144,8 @@ struct RepDesc {
     unsigned long long *ecoin;    // per tile 4 words: flip coin of the cluster at every edge position
     float2 *edge[2];         // spins before sweep t in slot t&1: per tile, its first column (TH) then first row (TW)
     double *partials;        // kNumSums planes of per-tile sums: partials[k * ntiles + tile]
+    double *partials2;       // chunk sums of the partials (deferred finalisation), kFinChunks x kNumSums
+    double *fourier;         // cos(2 pi x / L), sin(2 pi x / L) at [2x], [2x+1], x = 0 .. L-1
     RepState *st;
     int64_t L, N;
     int64_t ntiles, tile_base;  // tiles of this replica, first global tile id

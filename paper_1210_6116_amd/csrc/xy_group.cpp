@@ -169,6 +169,7 @@ int rebuild(xy_group *g)
         Slot &sl = g->slots[g->order[k]];
         if (!sl.needs_init) continue;
         GCHECK(g, xy::launch_init_spins(g->d_reps, k, sl.plan.res[0].N, sl.p.start, g->stream));
+        GCHECK(g, xy::launch_init_fourier(g->d_reps, k, sl.plan.res[0].L, g->stream));
         GCHECK(g, xy::launch_edge_refresh(g->d_reps, k, sl.plan.res[0].ntiles, g->stream));
         sl.needs_init = false;
     }

@@ -30,7 +30,7 @@ struct Resolved {
 
 // Per-replica byte layout inside an arena.
 struct RepLayout {
-    size_t c, s, lab[2], bx[2], by[2], bslot[2], node[2], cross[2], edge[2], ecoin, partials, end;
+    size_t c, s, lab[2], bx[2], by[2], bslot[2], node[2], cross[2], edge[2], ecoin, partials, partials2, fourier, end;
 };
 
 struct Plan {
@@ -70,9 +70,9 @@ hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int
         e = timer(XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, s); });
         if (e != hipSuccess) return e;
     }
-    e = timer(XY_K_MERGE, [&] { return xy::launch_merge(lc, true, pp.fin_pending ? &pp.fa_pending : nullptr, s); });
+    e = timer(XY_K_MERGE, [&] { return xy::launch_merge(lc, true, pp.fin_pending, s); });
     if (e != hipSuccess) return e;
-    e = timer(XY_K_COINS, [&] { return xy::launch_resolve(lc, s); });
+    e = timer(XY_K_COINS, [&] { return xy::launch_resolve(lc, pp.fin_pending ? &pp.fa_pending : nullptr, s); });
     if (e != hipSuccess) return e;
     pp.fin_pending = false;
     if (fuse_next) {

@@ -312,6 +312,20 @@ __device__ __forceinline__ void fold_sums(double (&v)[K], const double *red)
     }
 }
 
+// The Fourier sums from a lane's column sums (v[4], v[5] over the rows it
+// holds): every site of column x carries the same factor e^{i 2 pi x / L}.
+template <typename IT>
+__device__ __forceinline__ void fourier_terms(const RepDesc &R, IT x0, bool col, double (&v)[kNumSums])
+{
+    if (!col) return;
+    const XY_G double *f = gmem(R.fourier) + 2 * (x0 + (IT)(threadIdx.x & 63));
+    const double cs = f[0], sn = f[1];
+    v[6] = v[4] * cs;
+    v[7] = v[4] * sn;
+    v[8] = v[5] * cs;
+    v[9] = v[5] * sn;
+}
+
 __device__ __forceinline__ void store_partials(const RepDesc &R, int64_t lt, const double (&v)[kNumSums])
 {
     if (threadIdx.x == 0) {
@@ -330,6 +344,7 @@ __device__ __forceinline__ void obs_from_sums(const double *S, double N, double 
     o->ey = S[2] / N;
     o->sy = S[3] / N;
     o->ups_x = o->ex - beta * N * o->sx * o->sx;
+    o->mk2 = (S[6] * S[6] + S[7] * S[7] + S[8] * S[8] + S[9] * S[9]) / (N * N);
 }
 
 // --------------------------------------------------------------- init
@@ -357,6 +372,18 @@ __global__ __launch_bounds__(128) void k_edge_refresh(const RepDesc *__restrict_
     for (int k = threadIdx.x; k < T.TH + T.TW; k += blockDim.x) {
         const uint64_t i = k < T.TH ? T.site(k, 0) : T.site(0, k - T.TH);
         e[k] = make_float2(R.c[i], R.s[i]);
+    }
+}
+
+// (cos, sin)(2 pi x / L) of every column x, for the Fourier sums.
+__global__ __launch_bounds__(kThreads) void k_init_fourier(const RepDesc *__restrict__ reps, int32_t r)
+{
+    const RepDesc &R = reps[r];
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < R.L; x += (int64_t)gridDim.x * kThreads) {
+        double sn, cs;
+        sincospi(2.0 * (double)x / (double)R.L, &sn, &cs);
+        gmem(R.fourier)[2 * x] = cs;
+        gmem(R.fourier)[2 * x + 1] = sn;
     }
 }
 
@@ -389,7 +416,8 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     constexpr int BMAX = FIXED ? BT : 16;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = NW * 64;  // threads of the block: NW waves of BT rows (fixed tiles)
-    __shared__ double red[NW * kNumSums];
+    __shared__ double red[NW * kLinkSums];
+    __shared__ double colsum[FLIP ? NW * 64 * 2 : 1];
 
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
@@ -532,7 +560,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     }
 
     // ---- link sums of the flipped tile and / or link activation of sweep tb
-    double v[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double v[kLinkSums] = {};
     if constexpr (FLIP || BONDS) {
         BondCtx ctx;
         uint32_t key0 = 0, key1 = 0;
@@ -600,14 +628,49 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
             }
         }
     }
+    // the six link / site sums of the flipped tile: reduced per wave now,
+    // folded after the next barrier; the columns' sums of cos and sin go to LDS
+    // and one wave turns them into the four Fourier sums after that barrier
+    auto fold_tile_sums = [&]() {
+        if (threadIdx.x == 0) {
+            fold_sums<kLinkSums, NW>(v, red);
+#pragma unroll
+            for (int k = 0; k < kLinkSums; ++k) gmem(R.partials)[k * R.ntiles + lt] = v[k];
+        }
+        if (wave == NW - 1) {
+            double cs = 0.0, ss = 0.0;
+#pragma unroll
+            for (int w2 = 0; w2 < NW; ++w2) {
+                cs += colsum[(w2 * 64 + lane) * 2];
+                ss += colsum[(w2 * 64 + lane) * 2 + 1];
+            }
+            double f[4] = {0.0, 0.0, 0.0, 0.0};
+            if (lane < TW) {
+                const XY_G double *fo = gmem(R.fourier) + 2 * (T.x0 + (IT)lane);
+                const double ck = fo[0], sk = fo[1];
+                f[0] = cs * ck;
+                f[1] = cs * sk;
+                f[2] = ss * ck;
+                f[3] = ss * sk;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) f[k] += __shfl_xor(f[k], off);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) gmem(R.partials)[(kLinkSums + k) * R.ntiles + lt] = f[k];
+            }
+        }
+    };
     if constexpr (FLIP) {
-        wave_sums<kNumSums>(v, red);
+        colsum[(wave * 64 + lane) * 2] = lane < TW ? v[4] : 0.0;
+        colsum[(wave * 64 + lane) * 2 + 1] = lane < TW ? v[5] : 0.0;
+        wave_sums<kLinkSums>(v, red);
         if constexpr (!CCL) {
             __syncthreads();
-            if (threadIdx.x == 0) {
-                fold_sums<kNumSums, NW>(v, red);
-                store_partials(R, lt, v);
-            }
+            fold_tile_sums();
             return;
         }
     }
@@ -627,12 +690,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     if constexpr (!CCL) return;
 
     __syncthreads();
-    if constexpr (FLIP) {
-        if (threadIdx.x == 0) {
-            fold_sums<kNumSums, NW>(v, red);
-            store_partials(R, lt, v);
-        }
-    }
+    if constexpr (FLIP) fold_tile_sums();
     // smallest edge position per tile-local root, in the spin area (free now)
     uint32_t *smin = (uint32_t *)smem;
     const uint32_t NONE = 0xFFFFFFFFu;
@@ -774,22 +832,36 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
 // are contiguous (the edge's link mask and the two rows of edge slots); the
 // unions touch only the forest of boundary nodes.
 template <int NT>
-__device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red);
+__device__ void sum_partials(const RepDesc &R, int64_t j0, int64_t j1, double (&tot)[kNumSums], double *red);
+__device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, const double (&tot)[kNumSums]);
+
+// Deferred finalisation of a fused flip, in two stages on two kernels that
+// run anyway: kFinChunks blocks per replica beside the unions sum the tile
+// partials in chunks; one block per replica beside the edge coins sums the
+// chunks (fixed order) and finishes the sweep.
 
 __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ reps,
                                                      const uint32_t *__restrict__ tile_rep, int32_t nrep,
                                                      int64_t gtile0, int64_t gtile_end, int32_t next_dir,
-                                                     int64_t nblk, int32_t fin, FlipArgs fa)
+                                                     int64_t nfin)
 {
-    if (blockIdx.x >= nblk) {
-        // deferred finalisation of the previous sweep (its flip was fused):
-        // one extra block per replica, concurrent with the unions
+    // the first nfin blocks: deferred finalisation, stage 1 (chunk c of
+    // replica r; first in the grid, so that they overlap the unions)
+    if (blockIdx.x < nfin) {
         __shared__ double red[kWaves * kNumSums];
-        if (fin) finalize_rep<kThreads>(reps[blockIdx.x - nblk], fa, nullptr, red);
+        const int64_t b = blockIdx.x;
+        const RepDesc &R = reps[b / kFinChunks];
+        const int64_t c = b % kFinChunks;
+        double tot[kNumSums];
+        sum_partials<kThreads>(R, c * R.ntiles / kFinChunks, (c + 1) * R.ntiles / kFinChunks, tot, red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < kNumSums; ++k) gmem(R.partials2)[c * kNumSums + k] = tot[k];
+        }
         return;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
+    const int64_t gw = (int64_t)(blockIdx.x - nfin) * kWaves + wave;
     const int64_t gtile = gtile0 + (gw >> 1);
     const int edge = (int)(gw & 1);
     if (gtile >= gtile_end) return;
@@ -834,12 +906,28 @@ __global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ 
 // thread per edge position.
 __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict__ reps,
                                                        const uint32_t *__restrict__ tile_rep, int32_t nrep,
-                                                       int64_t gtile0)
+                                                       int64_t gtile0, int64_t nfin, FlipArgs fa)
 {
     __shared__ uint64_t sc[kWaves];
+    // the first nfin blocks: deferred finalisation, stage 2 (the chunks of
+    // replica r, then the sweep; first in the grid, to overlap the coins)
+    if (blockIdx.x < nfin) {
+        if (threadIdx.x == 0) {
+            const RepDesc &R = reps[blockIdx.x];
+            double tot[kNumSums];
+#pragma unroll
+            for (int k = 0; k < kNumSums; ++k) {
+                double a = 0.0;
+                for (int c = 0; c < kFinChunks; ++c) a += gmem(R.partials2)[c * kNumSums + k];
+                tot[k] = a;
+            }
+            finish_sweep(R, fa, nullptr, tot);
+        }
+        return;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t lt;
-    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + (blockIdx.x - nfin), lt);
     const uint64_t t = uniform_u64(gmem(R.st)->tl);
     const int par = (int)(t & 1);
     const int NB = R.nb;
@@ -864,34 +952,41 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
 // observables of the current configuration only (no counters touched).
 // Besides its own kernel, it runs in extra blocks of the merge kernel of the
 // next sweep when the flip was fused with that sweep's links.
+// Sums of the per-tile partials of replica R over the tiles [j0, j1), in a
+// fixed order (thread j takes tiles j0 + j, j0 + j + NT, ...); thread 0 gets
+// the totals.
 template <int NT>
-__device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red)
+__device__ void sum_partials(const RepDesc &R, int64_t j0, int64_t j1, double (&tot)[kNumSums], double *red)
 {
-    RepState *st = R.st;
-    double tot[kNumSums];
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) tot[k] = 0.0;
     const int64_t nt = R.ntiles;
+    const XY_G double *pt = gmem(R.partials);
     // four tiles per thread per round, their loads issued together
-    int64_t j = threadIdx.x;
-    for (; j + 3 * NT < nt; j += 4 * NT) {
+    int64_t j = j0 + threadIdx.x;
+    for (; j + 3 * NT < j1; j += 4 * NT) {
         double x[4][kNumSums];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int k = 0; k < kNumSums; ++k) x[q][k] = gmem(R.partials)[k * nt + j + q * NT];
+            for (int k = 0; k < kNumSums; ++k) x[q][k] = pt[k * nt + j + q * NT];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int k = 0; k < kNumSums; ++k) tot[k] += x[q][k];
     }
-    for (; j < nt; j += NT) {
+    for (; j < j1; j += NT) {
 #pragma unroll
-        for (int k = 0; k < kNumSums; ++k) tot[k] += gmem(R.partials)[k * nt + j];
+        for (int k = 0; k < kNumSums; ++k) tot[k] += pt[k * nt + j];
     }
     block_sum<kNumSums, NT / 64>(tot, red);
-    if (threadIdx.x != 0) return;
+}
 
+// Observables from the totals, the PCC window / beta step and the sweep
+// counter (one thread).  measure_out != null: observables only.
+__device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, const double (&tot)[kNumSums])
+{
+    RepState *st = R.st;
     const uint64_t t = st->t;
     const double beta = st->beta;
     const double N = (double)R.N;
@@ -921,6 +1016,7 @@ __device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
         acc[5] += o.sy;
         acc[6] += o.ups_x;
         acc[7] += N * o.sx * o.sx;
+        acc[8] += o.mk2;
         st->acc_n += 1;
         if (st->acc_n >= fa.window) {
             const double W = (double)fa.window;
@@ -944,6 +1040,7 @@ __device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
                 m.ey = acc[4] / W;
                 m.sy = acc[5] / W;
                 m.ups_x = acc[6] / W;
+                m.mk2 = acc[8] / W;
                 m.near_ties = 0;
                 fa.wmean[fa.wrow * fa.nrep + R.idx] = m;
             }
@@ -951,11 +1048,19 @@ __device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
             st->beta_sum += nb;
             st->beta_n += 1;
             st->pcc_k += 1;
-            for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+            for (int k = 0; k < 9; ++k) acc[k] = 0.0;
             st->acc_n = 0;
         }
     }
     st->t = t + 1;
+}
+
+template <int NT>
+__device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red)
+{
+    double tot[kNumSums];
+    sum_partials<NT>(R, 0, R.ntiles, tot, red);
+    if (threadIdx.x == 0) finish_sweep(R, fa, measure_out, tot);
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restrict__ reps, FlipArgs fa,
@@ -978,7 +1083,7 @@ __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int B = band_rows(T.TH), yb = wave * B;
     const IT Lm = T.L - 1;
-    double v[kNumSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double v[kNumSums] = {};
     for (int k = 0; k < B; ++k) {
         const int y = yb + k;
         if (y < T.TH && lane < T.TW) {
@@ -995,6 +1100,7 @@ __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict_
             v[5] += si;
         }
     }
+    fourier_terms(R, T.x0, lane < T.TW, v);
     block_sum<kNumSums, kWaves>(v, red);
     store_partials(R, lt, v);
 }
@@ -1042,6 +1148,13 @@ hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_
 {
     const int64_t blocks = std::min<int64_t>((N + kThreads - 1) / kThreads, kMaxStrideBlocks);
     hipLaunchKernelGGL(k_init_spins, dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, start);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_fourier(const RepDesc *d_reps, int32_t r, int64_t L, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_fourier, dim3((unsigned)((L + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d_reps,
+                       r);
     return hipGetLastError();
 }
 
@@ -1098,23 +1211,26 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const Launch &lc, bool next_dir, const FlipArgs *fin, hipStream_t s)
+hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s)
 {
     const int64_t waves = 2 * (lc.gtile_end - lc.gtile0);
     const int64_t nblk = (waves + kWaves - 1) / kWaves;
-    FlipArgs fa;
-    if (fin) fa = *fin;
-    else std::memset(&fa, 0, sizeof fa);
-    const dim3 grid((unsigned)(nblk + (fin ? lc.nrep : 0))), block(kThreads);
+    const int64_t nfin = fin ? (int64_t)lc.nrep * kFinChunks : 0;
+    const dim3 grid((unsigned)(nblk + nfin)), block(kThreads);
     hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end,
-                       (int32_t)next_dir, nblk, (int32_t)(fin != nullptr), fa);
+                       (int32_t)next_dir, nfin);
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const Launch &lc, hipStream_t s)
+hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(lc.gtile_end - lc.gtile0)), dim3(kThreads), 0, s, lc.reps,
-                       lc.tile_rep, lc.nrep, lc.gtile0);
+    const int64_t ntile = lc.gtile_end - lc.gtile0;
+    FlipArgs fa;
+    if (fin) fa = *fin;
+    else std::memset(&fa, 0, sizeof fa);
+    const int64_t nfin = fin ? lc.nrep : 0;
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(ntile + nfin)), dim3(kThreads), 0, s, lc.reps, lc.tile_rep,
+                       lc.nrep, lc.gtile0, nfin, fa);
     return hipGetLastError();
 }
 

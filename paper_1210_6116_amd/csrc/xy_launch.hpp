@@ -41,14 +41,16 @@ struct FlipArgs {
 
 hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s);
 hipError_t launch_edge_refresh(const RepDesc *d_reps, int32_t r, int64_t ntiles, hipStream_t s);
+hipError_t launch_init_fourier(const RepDesc *d_reps, int32_t r, int64_t L, hipStream_t s);
 hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s);
 hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s);
-// Union across tile edges; next_dir: also draw the next sweep's direction;
-// fin != null: also the deferred finalisation (one extra block per replica)
-// of the previous, fused sweep.
-hipError_t launch_merge(const Launch &lc, bool next_dir, const FlipArgs *fin, hipStream_t s);
-// Coins of the clusters at tile edges, after the merge.
-hipError_t launch_resolve(const Launch &lc, hipStream_t s);
+// Union across tile edges; next_dir: also draw the next sweep's direction.
+// fin: also the first stage of the deferred finalisation of the previous,
+// fused sweep (the second runs with the edge coins, given its arguments).
+hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s);
+// Coins of the clusters at tile edges, after the merge; fin != null: the
+// second stage of a deferred finalisation.
+hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s);
 hipError_t launch_measure(const Launch &lc, hipStream_t s);
 hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out,
                            hipStream_t s);

@@ -20,7 +20,7 @@ import xyworkloads as wl
 pytestmark = pytest.mark.gpu
 
 OBS_TOL = 1e-10
-NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x")
+NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x", "mk2")
 
 
 def _gpu():

@@ -12,7 +12,7 @@ import xyworkloads as wl
 
 pytestmark = pytest.mark.gpu
 
-NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x")
+NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x", "mk2")
 
 
 def test_graph_replay_equals_sweeps():

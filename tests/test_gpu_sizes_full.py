@@ -28,7 +28,7 @@ import xyworkloads as wl
 pytestmark = pytest.mark.gpu
 
 OBS_TOL = 1e-10
-NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x")
+NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x", "mk2")
 
 
 def test_full_size_l4096_fused_sweeps():
@@ -159,6 +159,8 @@ def test_l65536_sampled_oracle_and_invariants():
     # 4. unit spins and observables from an FP64 recomputation of the sums
     print("L=65536 observables", flush=True)
     sums = np.zeros(6)
+    colc = torch.zeros(L, dtype=torch.float64, device=dev)
+    cols = torch.zeros(L, dtype=torch.float64, device=dev)
     norm_dev = 0.0
     for y0 in range(0, L, rows):
         lo, cnt = y0 * L, rows * L
@@ -172,11 +174,17 @@ def test_l65536_sampled_oracle_and_invariants():
                           float((cb * cd + sb * sd).sum()), float((sb * cd - cb * sd).sum()),
                           float(cb.sum()), float(sb.sum())])
         norm_dev = max(norm_dev, float((cb * cb + sb * sb - 1.0).abs().max()))
+        colc += cb.sum(dim=0)
+        cols += sb.sum(dim=0)
     assert norm_dev < 1e-6
     scx, ssx, scy, ssy, sc, ss = sums
     ref = {"E": -(scx + scy) / N, "m2": (sc * sc + ss * ss) / (N * float(N)), "ex": scx / N, "sx": ssx / N,
            "ey": scy / N, "sy": ssy / N}
     ref["ups_x"] = ref["ex"] - beta * N * ref["sx"] ** 2
+    kx = 2.0 * np.pi * np.arange(L) / L
+    cc, cs = colc.cpu().numpy(), cols.cpu().numpy()
+    ref["mk2"] = (np.dot(cc, np.cos(kx)) ** 2 + np.dot(cc, np.sin(kx)) ** 2 + np.dot(cs, np.cos(kx)) ** 2
+                  + np.dot(cs, np.sin(kx)) ** 2) / float(N) ** 2
     g = tr[0, 0]
     for name in NAMES:
         assert abs(float(g[name]) - ref[name]) <= OBS_TOL, (name, float(g[name]), ref[name])
