@@ -1,0 +1,70 @@
+"""End-to-end pin against the paper's printed numbers: the L = 64, 128, 256 rows of
+Table 1.
+
+The paper runs the generalized PCC with windows of 1000 sweeps, dbeta = 0.0005,
+60000 discarded sweeps and 4e6 measured sweeps (the simulation paragraph, Table
+1), and reports e.g. beta_KT(64) = 1.09167(25), <m^2> = 0.34924(29) and
+xi_2nd/L = 0.7464(11).  Here 64 independent replicas (same seed, different stream ids) run
+that controller in one batched handle, each for 60 discarded and 63 measured
+windows (4.03e6 measured sweeps in all).  Estimates: beta_KT = mean of the beta
+each measured window ran at; <m^2> = mean of the window means of m2; xi_2nd from
+chi(0)/chi(2 pi / L) = <m2>/<mk2> (the xi_2nd and chi(k) definitions).  Errors
+from the spread over the replicas; agreement is required within 3 combined
+standard errors.  Expected values: the paper's (tests/golden/table1.txt).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1.txt")
+
+
+def _row(L):
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            if int(f[0]) == L:
+                return [float(x) for x in f[1:7]]
+    raise KeyError(L)
+
+
+@pytest.mark.parametrize("L", [64, 128, 256])
+def test_table1_row(L):
+    import paper_1210_6116_amd as xy
+    nrep, discard, measured, W = 64, 60, 63, 1000
+    b_ref, b_err, m2_ref, m2_err, xi_ref, xi_err = _row(L)
+    print("Table 1 L=%d: %d replicas x (%d + %d) windows of %d sweeps" % (L, nrep, discard, measured, W), flush=True)
+    specs = [dict(L=L, beta=round(b_ref, 2), seed=0x7AB1E1 + L, rep=k) for k in range(nrep)]
+    lat = xy.Lattices(specs)
+    lat.pcc(discard, W, 0.0005, dbeta_min=0.0005)
+    b_start = np.array([lat.beta(k) for k in range(nrep)])
+    means = lat.pcc(measured, W, 0.0005, dbeta_min=0.0005, means=True)
+    lat.close()
+    # beta each measured window ran at: the start value, then the previous step's result
+    beta_run = np.vstack([b_start[None, :], means["beta"][:-1]])
+    b_rep = beta_run.mean(axis=0)
+    m2_rep = means["m2"].mean(axis=0)
+    mk2_rep = means["mk2"].mean(axis=0)
+
+    def xi_over_L(m2, mk2):
+        return math.sqrt(m2 / mk2 - 1.0) / (2.0 * math.sin(math.pi / L)) / L
+
+    def mean_err(a):
+        return float(a.mean()), float(a.std(ddof=1) / math.sqrt(len(a)))
+
+    b, be = mean_err(b_rep)
+    m2, m2e = mean_err(m2_rep)
+    xi = xi_over_L(m2_rep.mean(), mk2_rep.mean())
+    # error of the ratio estimator by leaving one replica out at a time
+    jk = np.array([xi_over_L(np.delete(m2_rep, k).mean(), np.delete(mk2_rep, k).mean()) for k in range(nrep)])
+    xie = float(math.sqrt((nrep - 1) / nrep * ((jk - jk.mean()) ** 2).sum()))
+    print("beta_KT %.5f(%.5f) paper %.5f(%.5f)" % (b, be, b_ref, b_err))
+    print("<m^2>   %.5f(%.5f) paper %.5f(%.5f)" % (m2, m2e, m2_ref, m2_err))
+    print("xi/L    %.4f(%.4f) paper %.4f(%.4f)" % (xi, xie, xi_ref, xi_err), flush=True)
+    assert abs(b - b_ref) <= 3.0 * math.hypot(be, b_err)
+    assert abs(m2 - m2_ref) <= 3.0 * math.hypot(m2e, m2_err)
+    assert abs(xi - xi_ref) <= 3.0 * math.hypot(xie, xi_err)
