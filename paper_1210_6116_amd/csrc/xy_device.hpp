@@ -66,6 +66,31 @@ __device__ __forceinline__ double uniform_f64(double v)
     return __longlong_as_double((long long)uniform_u64((uint64_t)__double_as_longlong(v)));
 }
 
+// Element i of a global array.  With 32-bit site indices (N <= 2^30) the byte
+// offset fits 32 bits, so the access can take a scalar base and one 32-bit
+// vector offset (shared by arrays of the same element size) instead of a
+// 64-bit vector address per access.
+template <typename T>
+__device__ __forceinline__ XY_G T &gel(XY_G T *base, uint32_t i)
+{
+    return *(XY_G T *)((XY_G char *)base + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ XY_G T &gel(XY_G T *base, uint64_t i)
+{
+    return base[i];
+}
+template <typename T>
+__device__ __forceinline__ const XY_G T &gel(const XY_G T *base, uint32_t i)
+{
+    return *(const XY_G T *)((const XY_G char *)base + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const XY_G T &gel(const XY_G T *base, uint64_t i)
+{
+    return base[i];
+}
+
 struct U4 {
     uint32_t x, y, z, w;
 };

@@ -438,8 +438,8 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         for (int k = 0; k < B; ++k) {
             if (own(k)) {
                 const IT i = T.site(yb + k, lane);
-                c0[k] = cp[i];
-                s0[k] = sp[i];
+                c0[k] = gel(cp, i);
+                s0[k] = gel(sp, i);
             }
         }
     }
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         uint32_t lv[BMAX];
 #pragma unroll
         for (int k = 0; k < B; ++k)
-            if (own(k)) lv[k] = lab[T.site(yb + k, lane)];
+            if (own(k)) lv[k] = gel(lab, T.site(yb + k, lane));
         // halo: right column and bottom row of the neighbouring tiles (spins
         // before the sweep from their edge copies, coins from their edge-position
         // coins), flipped here exactly as their owners flip them
@@ -533,8 +533,8 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
                                                : ((rcoin[l >> T.log2TW] >> (l & (uint32_t)(TW - 1))) & 1ull);
                 float c1, s1;
                 if (flip_one(f, c0[k], s0[k], c1, s1)) {
-                    cp[i] = c1;
-                    sp[i] = s1;
+                    gel(cp, i) = c1;
+                    gel(sp, i) = s1;
                 }
                 spin[(yb + k) * SS + lane] = make_float2(c1, s1);
             }
@@ -811,7 +811,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     for (int k = 0; k < B; ++k) {
         if (own(k)) {
             const uint32_t sl = smin[lr[k]];
-            labn[T.site(yb + k, lane)] = (uint16_t)(sl != NONE ? (kBoundary | sl) : lr[k]);
+            gel(labn, T.site(yb + k, lane)) = (uint16_t)(sl != NONE ? (kBoundary | sl) : lr[k]);
         }
     }
     if (wave == 0) {
@@ -840,7 +840,8 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
 // partials in chunks; one block per replica beside the edge coins sums the
 // chunks (fixed order) and finishes the sweep.
 
-__global__ __launch_bounds__(kThreads) void k_merge(const RepDesc *__restrict__ reps,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge(
+    const RepDesc *__restrict__ reps,
                                                      const uint32_t *__restrict__ tile_rep, int32_t nrep,
                                                      int64_t gtile0, int64_t gtile_end, int32_t next_dir,
                                                      int64_t nfin)
