@@ -51,6 +51,16 @@ __device__ __forceinline__ void stf2(XY_G float2 *p, float2 v)
         ((unsigned long long)__float_as_uint(v.y) << 32) | (unsigned long long)__float_as_uint(v.x);
 }
 
+// Read through the constant address space: for a uniform address this is a
+// scalar load, allowed only for data no kernel running it writes (the sweep
+// counter, direction and beta in the kernels that only read them).
+#define XY_C __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ T cload(const T *p)
+{
+    return *(const XY_C T *)p;
+}
+
 // Values that are the same in every lane (read from memory the kernel also
 // writes, so the compiler keeps them in vector registers) moved to scalar
 // registers, with everything derived from them.

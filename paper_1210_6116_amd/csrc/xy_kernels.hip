@@ -443,7 +443,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
             }
         }
     }
-    const uint64_t t = uniform_u64(st->t);
+    const uint64_t t = cload(&R.st->t);
     const int par = (int)(t & 1);
     const uint64_t tb = MODE == M_FUSED ? t + 1 : t;  // sweep whose links this launch activates
     const int pb = (int)(tb & 1);
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     if constexpr (FLIP) {
         const XY_G uint16_t *__restrict__ lab = gmem(R.lab[par]);
         const XY_G float2 *__restrict__ eg = gmem(R.edge[par]);
-        const double rx = uniform_f64(st->dir[par][0]), ry = uniform_f64(st->dir[par][1]);
+        const double rx = cload(&R.st->dir[par][0]), ry = cload(&R.st->dir[par][1]);
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
         const uint32_t tf = (uint32_t)t;
         auto flip_one = [&](bool f, float c0, float s0, float &c1, float &s1) -> bool {
@@ -565,9 +565,9 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         BondCtx ctx;
         uint32_t key0 = 0, key1 = 0;
         if constexpr (BONDS) {
-            ctx.rx = uniform_f64(st->dir[pb][0]);
-            ctx.ry = uniform_f64(st->dir[pb][1]);
-            ctx.beta = uniform_f64(st->beta);
+            ctx.rx = cload(&R.st->dir[pb][0]);
+            ctx.ry = cload(&R.st->dir[pb][1]);
+            ctx.beta = cload(&R.st->beta);
             ctx.rxf = (float)ctx.rx;
             ctx.ryf = (float)ctx.ry;
             ctx.b2f = (float)(2.0 * ctx.beta);
@@ -869,7 +869,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
     const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
-    const uint64_t t = uniform_u64(gmem(R.st)->tl);  // the sweep whose links were labelled last
+    const uint64_t t = cload(&R.st->tl);  // the sweep whose links were labelled last
     const int par = (int)(t & 1);
     const int NB = R.nb;
     const int nlinks = edge ? T.TW : T.TH;
@@ -929,7 +929,7 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + (blockIdx.x - nfin), lt);
-    const uint64_t t = uniform_u64(gmem(R.st)->tl);
+    const uint64_t t = cload(&R.st->tl);
     const int par = (int)(t & 1);
     const int NB = R.nb;
     const int p = threadIdx.x;
