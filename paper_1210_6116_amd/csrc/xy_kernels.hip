@@ -5,21 +5,25 @@
 // definitions of e and s; the simulation paragraph for the PCC parameters).
 //
 // The lattice is cut into tiles of 64 columns (one wave64 lane per column) by
-// TH rows; one 256-thread workgroup owns a tile and each of its four waves a
-// band of TH/4 rows.  A sweep t is:
+// TH rows; one workgroup owns a tile and each of its waves a band of rows.  A
+// sweep t is:
 //   k_tile<BONDS>  mirror-direction projections, link activation (bit planes),
-//                  in-tile union-find in LDS (row runs from wave ballots, then
-//                  vertical unions), tile-local labels, flip-coin table
-//   k_merge        union of the labels across every active link that leaves a
-//                  tile (lock-free; the larger root is always hooked under the
-//                  smaller one, so every final root is its cluster's minimum site)
-//   k_merge<COMPRESS> end labels of edge links pointed at their final roots
-//   k_tile<FLIP>   root lookup, reflection of flipped clusters in FP64 with one
-//                  rounding to the FP32 state, the six link / site sums of the
-//                  flipped state
+//                  in-tile union-find in LDS (row runs from wave ballots, a
+//                  scan-line pass, unions where a run meets two labels, band
+//                  seams), 16-bit tile-local labels, the tile's edge slots and
+//                  boundary nodes, the links over its right and bottom edges
+//   k_merge        union of the boundary nodes joined by every active link that
+//                  leaves a tile (lock-free 64-bit atomicMin on (key, node): the
+//                  root of a cluster carries its smallest site)
+//   k_resolve      coin of the cluster at every edge position of every tile
+//   k_tile<FLIP>   coins (a tile's own roots from its rows' Philox blocks, the
+//                  others from the edge coins), reflection of flipped clusters
+//                  in FP64 with one rounding to the FP32 state, the ten sums of
+//                  the flipped state
 //   k_finalize     per replica: observables, PCC window and beta step, counter
 // k_tile<FUSED> does FLIP for sweep t and BONDS for sweep t+1 in one pass over
-// the spins (used whenever beta cannot change in between).
+// the spins (whenever beta cannot change in between); the finalisation of such
+// a flip then runs in two stages beside the next merge and edge coins.
 // Built with -ffp-contract=off: the FP64 expressions below are evaluated
 // operation by operation, exactly as written.
 #include <hip/hip_runtime.h>

@@ -211,3 +211,25 @@ def test_wide_index_path_parity(L, nsweeps, monkeypatch):
 def test_wide_index_fused_parity(monkeypatch):
     monkeypatch.setenv("XY_WIDE_INDEX", "1")
     test_fused_multi_sweep_parity(128, 32, 64)
+
+
+def test_device_label_flatten_and_views():
+    # canonical labels written to caller-owned device memory in both widths,
+    # and the device views of the state and link planes, against the host copies
+    import torch
+    xy = _gpu()
+    L = 128
+    lat = xy.Lattices(dict(L=L, beta=1.12, seed=0xF1A7))
+    lat.sweep(3)
+    want = lat.labels()
+    assert np.array_equal(lat.labels_device(bits=64).cpu().numpy(), want)
+    assert np.array_equal(lat.labels_device(bits=32).cpu().numpy().view(np.uint32).astype(np.int64), want)
+    v = lat.views()
+    c, s = lat.get_state()
+    assert np.array_equal(v["cos"].cpu().numpy(), c) and np.array_equal(v["sin"].cpu().numpy(), s)
+    bx, by = lat.bonds()
+    assert np.array_equal(xy.unpack_bits(v["bx"].cpu().numpy().view(np.uint32), L * L), bx)
+    assert np.array_equal(xy.unpack_bits(v["by"].cpu().numpy().view(np.uint32), L * L), by)
+    assert v["sweep"] == 3 and v["L"] == L
+    torch.cuda.synchronize()
+    lat.close()
