@@ -104,22 +104,25 @@ __device__ __noinline__ bool bond_exact(float fci, float fsi, float fcj, float f
     return e < omu;
 }
 
-// FP32 decision with a guard band: for unit spins the FP32 value of exp(-x)
-// is within ~1e-6 (1 + beta) of the FP64 one, so outside |e - (1-u)| <= G
-// both precisions agree; inside it the FP64 decision is taken.
+// FP32 decision with a guard band.  With y = -(2 beta log2 e) a_i a_j,
+// exp(-x) = 2^y, and the link is active iff u < 1 - exp(-x), i.e. iff
+// d = w - (1 - 2^min(y, 0)) 2^32 < 0 for the Philox word w = u 2^32.  For
+// unit spins the FP32 value of d is within ~2e-6 (1 + beta) 2^32 of the exact
+// one, so outside |d| <= G 2^32 both precisions agree; inside it the FP64
+// decision is taken.
 struct BondCtx {
     double rx, ry, beta;
-    float rxf, ryf, b2f, guard;
+    float rxf, ryf, bl, gw;  // bl = -2 beta log2 e; gw = G 2^32
     unsigned long long *ties;
 };
 
-__device__ __forceinline__ bool bond_decide(const BondCtx &B, float ai, float aj, uint32_t w, float2 si, float2 sj)
+__device__ __forceinline__ float bond_proj(const BondCtx &B, float2 v) { return __builtin_fmaf(v.x, B.rxf, v.y * B.ryf); }
+
+// d for the link (i, j), given bai = bl a_i
+__device__ __forceinline__ float bond_margin(float bai, float aj, uint32_t w)
 {
-    const float xb = (B.b2f * ai) * aj;
-    const float e = xb > 0.0f ? __expf(-xb) : 1.0f;
-    const float omu = 1.0f - (float)w * 2.3283064365386963e-10f;
-    if (fabsf(e - omu) <= B.guard) return bond_exact(si.x, si.y, sj.x, sj.y, B.rx, B.ry, B.beta, w, B.ties);
-    return e < omu;
+    const float e = __builtin_amdgcn_exp2f(fminf(bai * aj, 0.0f));
+    return __builtin_fmaf(e, 4294967296.0f, (float)w - 4294967296.0f);
 }
 
 // Inclusive prefix maximum over the 64 lanes of a wave with DPP moves:
@@ -135,6 +138,15 @@ __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v)
     v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
     v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
     return v;
+}
+
+// Bit `lane` of the wave-uniform mask m selects a (set) or b, as one
+// v_cndmask with m as its lane mask.
+__device__ __forceinline__ uint32_t lane_select(uint64_t m, uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(m));
+    return r;
 }
 
 // ------------------------------------------------------- union-find in LDS
@@ -427,7 +439,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
     const Tile<IT> T = make_tile<IT>(R, lt);
     const int TW = FIXED ? 64 : T.TW, TH = FIXED ? NW * BT : T.TH, SS = TW + 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int B = FIXED ? BT : band_rows(TH), yb = wave * B;
     XY_G RepState *st = gmem(R.st);
     // site (yb + k, lane) belongs to this tile (always, for fixed tiles)
@@ -565,6 +577,9 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
 
     // ---- link sums of the flipped tile and / or link activation of sweep tb
     double v[kLinkSums] = {};
+    // link masks of the wave's own rows, kept in scalar registers (fixed tiles)
+    constexpr bool RMASK = FIXED && BONDS;
+    uint64_t xrow[RMASK ? BMAX : 1], yrow[RMASK ? BMAX : 1];
     if constexpr (FLIP || BONDS) {
         BondCtx ctx;
         uint32_t key0 = 0, key1 = 0;
@@ -574,8 +589,8 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
             ctx.beta = cload(&R.st->beta);
             ctx.rxf = (float)ctx.rx;
             ctx.ryf = (float)ctx.ry;
-            ctx.b2f = (float)(2.0 * ctx.beta);
-            ctx.guard = 1e-5f * (1.0f + (float)ctx.beta);
+            ctx.bl = (float)(-2.0 * ctx.beta * 1.4426950408889634);
+            ctx.gw = (float)(1e-5 * (1.0 + ctx.beta) * 4294967296.0);
             ctx.ties = (unsigned long long *)&st->ties[pb];
             key0 = (uint32_t)R.seed;
             key1 = (uint32_t)(R.seed >> 32);
@@ -583,12 +598,12 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         U4 w = {0u, 0u, 0u, 0u};
         // a row's values below are the next row's own: carried, not recomputed
         double cdn = 0.0, sdn = 0.0;
-        float adn = 0.0f;
+        float badn = 0.0f;  // bl a of the row below
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int y = yb + k;
             if (!FIXED && y >= TH) break;
-            bool xa = false, ya = false;
+            uint64_t mx = 0, my = 0;  // active links of the row (BONDS)
             if (FIXED || lane < TW) {
                 const float2 a = spin[y * SS + lane];
                 const float2 r = spin[y * SS + lane + 1];
@@ -613,21 +628,38 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
                     if (FIXED ? (k % 2 == 0) : (k == 0 || (gy & 1) == 0))
                         w = philox4x32_10((uint32_t)(((gy >> 1) << T.log2L) + T.x0 + (IT)lane), R.rep,
                                           (uint32_t)tb, TAG_BOND, key0, key1);
-                    const uint32_t wx = (gy & 1) ? w.z : w.x;
-                    const uint32_t wy = (gy & 1) ? w.w : w.y;
-                    const float ai = k == 0 ? a.x * ctx.rxf + a.y * ctx.ryf : adn;
-                    const float ar = r.x * ctx.rxf + r.y * ctx.ryf;
-                    const float ad = d.x * ctx.rxf + d.y * ctx.ryf;
-                    adn = ad;
-                    xa = bond_decide(ctx, ai, ar, wx, a, r);
-                    ya = bond_decide(ctx, ai, ad, wy, a, d);
+                    // fixed tiles start on even rows and bands have an even
+                    // number of rows, so the pair half is the row's parity in the band
+                    const bool odd = FIXED && BT % 2 == 0 ? (k & 1) : (gy & 1);
+                    const uint32_t wx = odd ? w.z : w.x;
+                    const uint32_t wy = odd ? w.w : w.y;
+                    const float bai = k == 0 ? ctx.bl * bond_proj(ctx, a) : badn;
+                    const float ad = bond_proj(ctx, d);
+                    badn = ctx.bl * ad;
+                    const float dx = bond_margin(bai, bond_proj(ctx, r), wx);
+                    const float dy = bond_margin(bai, ad, wy);
+                    mx = __ballot(dx < 0.0f);
+                    my = __ballot(dy < 0.0f);
+                    if (__ballot(fabsf(dx) <= ctx.gw) | __ballot(fabsf(dy) <= ctx.gw)) {
+                        // some lane inside the guard band (rare)
+                        bool xa = dx < 0.0f, ya = dy < 0.0f;
+                        if (fabsf(dx) <= ctx.gw)
+                            xa = bond_exact(a.x, a.y, r.x, r.y, ctx.rx, ctx.ry, ctx.beta, wx, ctx.ties);
+                        if (fabsf(dy) <= ctx.gw)
+                            ya = bond_exact(a.x, a.y, d.x, d.y, ctx.rx, ctx.ry, ctx.beta, wy, ctx.ties);
+                        mx = __ballot(xa);
+                        my = __ballot(ya);
+                    }
                 }
             }
             if constexpr (BONDS) {
-                const uint64_t mx = __ballot(xa), my = __ballot(ya);
                 if (lane == 0) {
                     bxm[y] = mx;
                     bym[y] = my;
+                }
+                if constexpr (RMASK) {
+                    xrow[k] = mx;
+                    yrow[k] = my;
                 }
             }
         }
@@ -734,6 +766,14 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     const uint64_t twmask = TW == 64 ? ~0ull : ((1ull << (TW & 63)) - 1ull);
     const uint64_t inner = twmask >> 1;  // link x -> x+1 stays inside the tile
     const uint64_t below = (1ull << lane) - 1ull;
+    auto xrow_mask = [&](int k) -> uint64_t {
+        if constexpr (RMASK) return xrow[k];
+        else return uniform_u64(bxm[yb + k]);
+    };
+    auto yrow_mask = [&](int k) -> uint64_t {
+        if constexpr (RMASK) return yrow[k];
+        else return uniform_u64(bym[yb + k]);
+    };
     // 1) each wave scans its band of rows top-down.  A run of x-links takes
     //    the smallest label among the runs above that it touches through a
     //    y-link (segmented prefix minimum over the run's lanes, then read at
@@ -746,28 +786,29 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         const int y = yb + k;
         if (!FIXED && y >= TH) break;
         const bool act = FIXED || lane < TW;
-        const uint64_t xm = bxm[y] & inner;
-        const uint64_t brk = ~xm & below;
-        const int start = brk ? 64 - __clzll((long long)brk) : 0;
-        const int end = __ffsll((long long)(~xm & ~below)) - 1;
-        uint32_t cand = NONE;
-        if (k > 0 && act && ((bym[y - 1] >> lane) & 1ull)) cand = lprev;
+        const uint64_t xm = xrow_mask(k) & inner;
+        const uint64_t ends = ~xm;  // bit x: the run through x ends at x
+        const uint32_t end = (uint32_t)__builtin_ctzll(ends & ~below);
         // segmented minimum as an unsegmented maximum of (run index, 0xFFFF - label):
         // run indices grow with the lane, so a lane's prefix maximum comes from
-        // its own run; labels of a tile are below 2^12
-        const uint32_t run_id = (uint32_t)__popcll(brk);
-        const uint32_t key = (run_id << 16) | (0xFFFFu - (cand == NONE ? 0xFFFFu : cand));
-        const uint32_t pm = __shfl(wave_prefix_max(key), end & 63);
-        const uint32_t low = 0xFFFFu - (pm & 0xFFFFu);
-        const uint32_t m = low == 0xFFFFu ? NONE : low;
-        const uint32_t lab = m != NONE ? m : (uint32_t)(y * TW + start);
-        // a run's lanes below one run above share their candidate: only the
-        // first of them records its union
-        const uint32_t cleft = __shfl_up(cand, 1);
-        const bool again = lane > start && cleft == cand;
-        if (act) {
-            lab_s[y * TW + lane] = lab;
-            if (cand != NONE && cand != m && !again) union_lds(lab_s, cand, m);
+        // its own run.  A lane offers the label above it (through a y-link) or
+        // else its own site; labels above are smaller than the row's sites, so
+        // the run's minimum is the smallest label above, or else its first site.
+        // Labels of a tile are below 2^12.
+        const uint64_t up = k > 0 ? yrow_mask(k - 1) : 0ull;  // lanes with a y-link from above
+        const uint32_t c2 = lane_select(up, lprev, (uint32_t)(y * TW) + (uint32_t)lane);
+        const uint32_t run_id = __builtin_amdgcn_mbcnt_hi((uint32_t)(ends >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)ends, 0u));
+        const uint32_t key = (run_id << 16) | (0xFFFFu - c2);
+        const uint32_t pm = __shfl(wave_prefix_max(key), (int)end);
+        const uint32_t lab = 0xFFFFu - (pm & 0xFFFFu);
+        if (act) lab_s[y * TW + lane] = lab;
+        if (k > 0) {
+            // a lane whose label above differs from its run's records their
+            // union, unless its left neighbour in the run offers the same label
+            const uint32_t cleft = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE, (int)c2, 0x138, 0xf, 0xf, false);  // wave_shr:1
+            const uint64_t need = up & __ballot(c2 != lab) & ~((xm << 1) & __ballot(cleft == c2));
+            if (lane_select(need, 1u, 0u)) union_lds(lab_s, c2, lab);
         }
         lprev = lab;
     }
