@@ -76,6 +76,15 @@ __device__ __forceinline__ double uniform_f64(double v)
     return __longlong_as_double((long long)uniform_u64((uint64_t)__double_as_longlong(v)));
 }
 
+// A value computed in vector registers from scalars (there are no scalar FP
+// conversions), moved back to a scalar register.
+__device__ __forceinline__ float uniform_f32(float v)
+{
+    float r;
+    asm("v_readfirstlane_b32 %0, %1" : "=s"(r) : "v"(v));
+    return r;
+}
+
 // Element i of a global array.  With 32-bit site indices (N <= 2^30) the byte
 // offset fits 32 bits, so the access can take a scalar base and one 32-bit
 // vector offset (shared by arrays of the same element size) instead of a
@@ -135,7 +144,6 @@ __device__ __forceinline__ double unif64(uint32_t w) { return (double)w * (1.0 /
 // Scx, Ssx, Scy, Ssy, sum cos, sum sin, then the Fourier sums at k = 2 pi / L
 // along x: sum cos e^{ikx} (real, imaginary), sum sin e^{ikx} (real, imaginary)
 constexpr int kNumSums = 10;
-constexpr int kLinkSums = 6;  // the first six
 constexpr int kFinChunks = 8; // chunks of the two-stage (deferred) finalisation
 
 struct RepState {
@@ -156,7 +164,7 @@ struct RepState {
 
 // Labels of sweep t (slot t&1 of every double buffer below):
 //   lab[i]   16 bits per site, tile-local: the tile-local index y*TW + x of the
-//            smallest site of i's component inside its tile, or kBoundary | s
+//            smallest site of i's component inside its tile, or TW*TH + s
 //            when that component touches the tile's edge, s being its slot
 //   bslot    per tile NB = 2*(TW+TH) bytes: for every edge position p (top row,
 //            bottom row, left column, right column) the slot of its component,
@@ -168,7 +176,6 @@ struct RepState {
 //            over the bottom edge (bit x)
 //   ecoin    per tile four words (one buffer): bit p = flip coin of the cluster
 //            at edge position p, drawn between the merge and the flip
-constexpr uint32_t kBoundary = 0x8000u;
 
 struct RepDesc {
     float *c, *s;            // spin planes, N floats each

@@ -299,9 +299,9 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *red /* NW*K */
     }
 }
 
-// First half of block_sum: each wave's sums into red[wave * K + k]; a later
-// barrier and fold_sums finish it (the tile kernel reuses a barrier it needs
-// anyway).
+// First half of block_sum: each wave's sums into red[wave * K + k]; after a
+// later barrier the sums over the waves finish it (the tile kernel reuses a
+// barrier it needs anyway).
 template <int K>
 __device__ __forceinline__ void wave_sums(double (&v)[K], double *red)
 {
@@ -314,17 +314,6 @@ __device__ __forceinline__ void wave_sums(double (&v)[K], double *red)
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
-    }
-}
-
-template <int K, int NW>
-__device__ __forceinline__ void fold_sums(double (&v)[K], const double *red)
-{
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = red[k];
-        for (int w2 = 1; w2 < NW; ++w2) s += red[w2 * K + k];
-        v[k] = s;
     }
 }
 
@@ -421,7 +410,7 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
 // issued together); BT = 0 is the general path (4 waves) for lattices
 // narrower than 64 and for batches of mixed tile shapes.
 template <typename IT, int MODE, int BT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ reps,
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) void k_tile(const RepDesc *__restrict__ reps,
                                                     const uint32_t *__restrict__ tile_rep,
                                                     int32_t nrep, int64_t gtile0)
 {
@@ -432,8 +421,8 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     constexpr int BMAX = FIXED ? BT : 16;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = NW * 64;  // threads of the block: NW waves of BT rows (fixed tiles)
-    __shared__ double red[NW * kLinkSums];
-    __shared__ double colsum[FLIP ? NW * 64 * 2 : 1];
+    constexpr int kPairSums = 4;  // link sums: cos and sin of the x links, of the y links
+    __shared__ double red[NW * kPairSums];
 
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
@@ -464,12 +453,15 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     const uint64_t tb = MODE == M_FUSED ? t + 1 : t;  // sweep whose links this launch activates
     const int pb = (int)(tb & 1);
 
+    // spin area: the spins with their halo; after the link pass the edge-slot
+    // table and the waves' column sums
     float2 *spin = (float2 *)smem;
-    uint64_t *bxm = (uint64_t *)(spin + (TH + 1) * SS);
+    const int sarea = max((TH + 1) * SS * (int)sizeof(float2), TW * TH * (int)sizeof(uint32_t) + NT * 16);
+    uint64_t *bxm = (uint64_t *)(smem + sarea);
     uint64_t *bym = bxm + TH;
-    uint64_t *scoin = bym + TH;  // 4 words: coins of the edge positions
-    uint64_t *rcoin = scoin + 4; // TH words: coins of the tile's rows
-    uint32_t *lab_s = (uint32_t *)(rcoin + TH);
+    uint64_t *rcoin = bym + TH;   // TH words: coins of the tile's rows
+    uint64_t *scoin = rcoin + TH; // 4 words: coins of the edge positions
+    uint32_t *lab_s = (uint32_t *)(scoin + 4);
     const int64_t ecount = TH + TW;
 
     if constexpr (FLIP) {
@@ -479,19 +471,20 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
         const uint32_t tf = (uint32_t)t;
         auto flip_one = [&](bool f, float c0, float s0, float &c1, float &s1) -> bool {
-            double c = c0, s = s0;
+            c1 = c0;
+            s1 = s0;
             if (f) {
+                const double c = c0, s = s0;
                 const double g = 2.0 * (c * rx + s * ry);
-                c = (double)(float)(c - g * rx);
-                s = (double)(float)(s - g * ry);
+                c1 = (float)(c - g * rx);
+                s1 = (float)(s - g * ry);
             }
             if (renorm) {
+                const double c = c1, s = s1;
                 const double n = sqrt(c * c + s * s);
-                c = (double)(float)(c / n);
-                s = (double)(float)(s / n);
+                c1 = (float)(c / n);
+                s1 = (float)(s / n);
             }
-            c1 = (float)c;
-            s1 = (float)s;
             return f || renorm;
         };
         // labels of the wave's rows
@@ -522,7 +515,8 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         // coin of edge position p, drawn after the merge; a boundary label
         // names its slot, itself an edge position), and of clusters inside the
         // tile (rooted at one of its sites): the Philox block holding a row's
-        // sites, bit x of rcoin[y] for site (y, x)
+        // sites, bit x of rcoin[y] for site (y, x).  For 64-column tiles the two
+        // arrays are one bit string indexed by the label.
         if (threadIdx.x < 4) scoin[threadIdx.x] = ec[lt * 4 + threadIdx.x];
         if (threadIdx.x >= 64 && threadIdx.x < 64 + TH) {
             const int y = threadIdx.x - 64;
@@ -545,8 +539,14 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
             if (own(k)) {
                 const IT i = T.site(yb + k, lane);
                 const uint32_t l = lv[k];
-                const bool f = (l & kBoundary) ? ((scoin[(l & 0xFFu) >> 6] >> (l & 63u)) & 1ull)
-                                               : ((rcoin[l >> T.log2TW] >> (l & (uint32_t)(TW - 1))) & 1ull);
+                bool f;
+                if constexpr (FIXED) {
+                    f = (((const uint32_t *)rcoin)[l >> 5] >> (l & 31u)) & 1u;
+                } else {
+                    const uint32_t nsite = (uint32_t)(TW * TH), q = l - nsite;
+                    f = l >= nsite ? ((scoin[q >> 6] >> (q & 63u)) & 1ull)
+                                   : ((rcoin[l >> T.log2TW] >> (l & (uint32_t)(TW - 1))) & 1ull);
+                }
                 float c1, s1;
                 if (flip_one(f, c0[k], s0[k], c1, s1)) {
                     gel(cp, i) = c1;
@@ -576,7 +576,8 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     }
 
     // ---- link sums of the flipped tile and / or link activation of sweep tb
-    double v[kLinkSums] = {};
+    double v[kPairSums] = {};
+    double cs = 0.0, ss = 0.0;  // the lane's column sums of cos and sin
     // link masks of the wave's own rows, kept in scalar registers (fixed tiles)
     constexpr bool RMASK = FIXED && BONDS;
     uint64_t xrow[RMASK ? BMAX : 1], yrow[RMASK ? BMAX : 1];
@@ -617,8 +618,8 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
                     v[1] = fma(si, cr, fma(-ci, sr, v[1]));
                     v[2] = fma(ci, cd, fma(si, sd, v[2]));
                     v[3] = fma(si, cd, fma(-ci, sd, v[3]));
-                    v[4] += ci;
-                    v[5] += si;
+                    cs += ci;
+                    ss += si;
                     cdn = cd;
                     sdn = sd;
                 }
@@ -664,49 +665,58 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
             }
         }
     }
-    // the six link / site sums of the flipped tile: reduced per wave now,
-    // folded after the next barrier; the columns' sums of cos and sin go to LDS
-    // and one wave turns them into the four Fourier sums after that barrier
-    auto fold_tile_sums = [&]() {
-        if (threadIdx.x == 0) {
-            fold_sums<kLinkSums, NW>(v, red);
+    // sums of the flipped tile.  The four link sums are reduced per wave now
+    // and folded by thread 0 after the next barrier.  The column sums of cos
+    // and sin go to the spin area after that barrier (the spins are read by
+    // then), behind the edge-slot table; after the following barrier the last
+    // wave adds them up per column, forms the four Fourier sums (every site of
+    // column x carries e^{i 2 pi x / L}) and reduces those and the two site sums.
+    double *colsum = (double *)(smem + (size_t)TW * TH * sizeof(uint32_t));
+    auto fold_link_sums = [&]() {
+        if (threadIdx.x < kPairSums) {
+            const int k = threadIdx.x;
+            double a = red[k];
 #pragma unroll
-            for (int k = 0; k < kLinkSums; ++k) gmem(R.partials)[k * R.ntiles + lt] = v[k];
+            for (int w2 = 1; w2 < NW; ++w2) a += red[w2 * kPairSums + k];
+            gmem(R.partials)[k * R.ntiles + lt] = a;
         }
+        colsum[(wave * 64 + lane) * 2] = lane < TW ? cs : 0.0;
+        colsum[(wave * 64 + lane) * 2 + 1] = lane < TW ? ss : 0.0;
+    };
+    auto fold_site_sums = [&]() {
         if (wave == NW - 1) {
-            double cs = 0.0, ss = 0.0;
+            double f[6] = {colsum[lane * 2], colsum[lane * 2 + 1], 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int w2 = 0; w2 < NW; ++w2) {
-                cs += colsum[(w2 * 64 + lane) * 2];
-                ss += colsum[(w2 * 64 + lane) * 2 + 1];
+            for (int w2 = 1; w2 < NW; ++w2) {
+                f[0] += colsum[(w2 * 64 + lane) * 2];
+                f[1] += colsum[(w2 * 64 + lane) * 2 + 1];
             }
-            double f[4] = {0.0, 0.0, 0.0, 0.0};
             if (lane < TW) {
                 const XY_G double *fo = gmem(R.fourier) + 2 * (T.x0 + (IT)lane);
                 const double ck = fo[0], sk = fo[1];
-                f[0] = cs * ck;
-                f[1] = cs * sk;
-                f[2] = ss * ck;
-                f[3] = ss * sk;
+                f[2] = f[0] * ck;
+                f[3] = f[0] * sk;
+                f[4] = f[1] * ck;
+                f[5] = f[1] * sk;
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 6; ++k) {
 #pragma unroll
                 for (int off = 32; off > 0; off >>= 1) f[k] += __shfl_xor(f[k], off);
             }
             if (lane == 0) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) gmem(R.partials)[(kLinkSums + k) * R.ntiles + lt] = f[k];
+                for (int k = 0; k < 6; ++k) gmem(R.partials)[(kPairSums + k) * R.ntiles + lt] = f[k];
             }
         }
     };
     if constexpr (FLIP) {
-        colsum[(wave * 64 + lane) * 2] = lane < TW ? v[4] : 0.0;
-        colsum[(wave * 64 + lane) * 2 + 1] = lane < TW ? v[5] : 0.0;
-        wave_sums<kLinkSums>(v, red);
+        wave_sums<kPairSums>(v, red);
         if constexpr (!CCL) {
             __syncthreads();
-            fold_tile_sums();
+            fold_link_sums();
+            __syncthreads();
+            fold_site_sums();
             return;
         }
     }
@@ -726,7 +736,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     if constexpr (!CCL) return;
 
     __syncthreads();
-    if constexpr (FLIP) fold_tile_sums();
+    if constexpr (FLIP) fold_link_sums();
     // smallest edge position per tile-local root, in the spin area (free now)
     uint32_t *smin = (uint32_t *)smem;
     const uint32_t NONE = 0xFFFFFFFFu;
@@ -813,6 +823,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
         lprev = lab;
     }
     __syncthreads();
+    if constexpr (FLIP) fold_site_sums();
     // 2) the seams between bands: y-links from a wave's last row; a link
     //    whose left neighbour joins the same two runs is skipped
     {
@@ -856,7 +867,7 @@ __global__ __launch_bounds__(NW * 64) void k_tile(const RepDesc *__restrict__ re
     for (int k = 0; k < B; ++k) {
         if (own(k)) {
             const uint32_t sl = smin[lr[k]];
-            gel(labn, T.site(yb + k, lane)) = (uint16_t)(sl != NONE ? (kBoundary | sl) : lr[k]);
+            gel(labn, T.site(yb + k, lane)) = (uint16_t)(sl != NONE ? (uint32_t)(TW * TH) + sl : lr[k]);
         }
     }
     if (wave == 0) {
@@ -1165,9 +1176,10 @@ __global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict_
         const IT y = (IT)i >> R.log2L, x = (IT)i & (IT)(R.L - 1);
         const int64_t lt = (int64_t)(y >> log2TH) * R.ntx + (int64_t)(x >> R.log2TW);
         const uint32_t l = gmem(R.lab[q])[i];
+        const uint32_t nsite = (uint32_t)R.TH << R.log2TW;
         uint64_t key;
-        if (l & kBoundary) {
-            key = root_key(gmem(R.node[q]), (uint32_t)(lt * R.nb) + (l & 0xFFu));
+        if (l >= nsite) {
+            key = root_key(gmem(R.node[q]), (uint32_t)(lt * R.nb) + (l - nsite));
         } else {
             const Tile<IT> T = make_tile<IT>(R, lt);
             key = (uint64_t)T.site_of_local((int)l);
@@ -1182,8 +1194,11 @@ __global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict_
 // ====================================================== host-side launchers
 size_t lds_bytes_tile(int TH)
 {
-    return (size_t)(TH + 1) * 65 * sizeof(float2) + (size_t)(3 * TH + 4) * sizeof(uint64_t) +
-           (size_t)64 * TH * sizeof(uint32_t);
+    // spin area: the spins with their halo, later the edge-slot table and the
+    // column sums of the waves (8 waves for 64-row tiles, else 4)
+    const size_t spins = (size_t)(TH + 1) * 65 * sizeof(float2);
+    const size_t later = (size_t)64 * TH * sizeof(uint32_t) + (size_t)(TH >= 64 ? 8 : 4) * 64 * 2 * sizeof(double);
+    return std::max(spins, later) + (size_t)(3 * TH + 4) * sizeof(uint64_t) + (size_t)64 * TH * sizeof(uint32_t);
 }
 
 // Element-wise kernels over N sites loop with a grid stride: a dispatch holds
