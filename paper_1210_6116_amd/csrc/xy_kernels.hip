@@ -959,13 +959,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
 // component) finds the smallest site of its cluster and draws that cluster's
 // flip coin; then every edge position takes the coin of its slot.  Bit p of
 // ecoin[4 * tile + p / 64] is the coin of the cluster at edge position p (a
-// boundary label's slot is itself an edge position).  One block per tile, one
-// thread per edge position.
+// boundary label's slot is itself an edge position).  One wave per tile: lane
+// l holds positions l, l + 64, l + 128, l + 192 (NB <= 256), walks their
+// paths to the roots together, and the coins are exchanged by ballots.
 __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict__ reps,
                                                        const uint32_t *__restrict__ tile_rep, int32_t nrep,
-                                                       int64_t gtile0, int64_t nfin, FlipArgs fa)
+                                                       int64_t gtile0, int64_t gtile_end, int64_t nfin, FlipArgs fa)
 {
-    __shared__ uint64_t sc[kWaves];
     // the first nfin blocks: deferred finalisation, stage 2 (the chunks of
     // replica r, then the sweep; first in the grid, to overlap the coins)
     if (blockIdx.x < nfin) {
@@ -982,25 +982,56 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
         }
         return;
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int G = 4;  // groups of 64 edge positions
+    const int lane = threadIdx.x & 63;
+    const int64_t gtile = gtile0 + (int64_t)(blockIdx.x - nfin) * kWaves + (threadIdx.x >> 6);
+    if (gtile >= gtile_end) return;
     int64_t lt;
-    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + (blockIdx.x - nfin), lt);
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
     const uint64_t t = cload(&R.st->tl);
     const int par = (int)(t & 1);
     const int NB = R.nb;
-    const int p = threadIdx.x;
-    uint32_t sl = 0;
-    bool cb = false;
-    if (p < NB) {
-        sl = gmem(R.bslot[par])[lt * NB + p];
-        if (sl == (uint32_t)p) cb = coin_of(R, (uint32_t)t, root_key(gmem(R.node[par]), (uint32_t)(lt * NB + p)));
+    const XY_G uint8_t *bs = gmem(R.bslot[par]) + lt * NB;
+    const XY_G unsigned long long *P = gmem(R.node[par]);
+    uint32_t sl[G], n[G];
+    unsigned long long e[G];
+    bool used[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int p = g * 64 + lane;
+        sl[g] = p < NB ? bs[p] : 0u;
     }
-    const uint64_t m = __ballot(cb);
-    if (lane == 0) sc[wave] = m;
-    __syncthreads();
-    const bool pc = p < NB && ((sc[sl >> 6] >> (sl & 63u)) & 1ull);
-    const uint64_t m2 = __ballot(pc);
-    if (lane == 0) gmem(R.ecoin)[lt * 4 + wave] = m2;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int p = g * 64 + lane;
+        used[g] = p < NB && sl[g] == (uint32_t)p;
+        n[g] = (uint32_t)(lt * NB + p);
+        e[g] = used[g] ? P[n[g]] : 0ull;
+    }
+    // roots: a root's entry names itself and holds the cluster's smallest site
+    while (true) {
+        bool more = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) more = more || (used[g] && (uint32_t)e[g] != n[g]);
+        if (!__ballot(more)) break;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (used[g] && (uint32_t)e[g] != n[g]) {
+                n[g] = (uint32_t)e[g];
+                e[g] = P[n[g]];
+            }
+        }
+    }
+    uint64_t cm[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) cm[g] = __ballot(used[g] && coin_of(R, (uint32_t)t, (uint32_t)(e[g] >> 32)));
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t q = sl[g] >> 6;
+        const uint64_t w = q == 0 ? cm[0] : q == 1 ? cm[1] : q == 2 ? cm[2] : cm[3];
+        const uint64_t m2 = __ballot(g * 64 + lane < NB && ((w >> (sl[g] & 63u)) & 1ull));
+        if (lane == 0) gmem(R.ecoin)[lt * 4 + g] = m2;
+    }
 }
 
 // ------------------------------------------------- finalise a sweep
@@ -1290,8 +1321,8 @@ hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s)
     if (fin) fa = *fin;
     else std::memset(&fa, 0, sizeof fa);
     const int64_t nfin = fin ? lc.nrep : 0;
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(ntile + nfin)), dim3(kThreads), 0, s, lc.reps, lc.tile_rep,
-                       lc.nrep, lc.gtile0, nfin, fa);
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)((ntile + kWaves - 1) / kWaves + nfin)), dim3(kThreads), 0, s,
+                       lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, nfin, fa);
     return hipGetLastError();
 }
 
