@@ -113,24 +113,26 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         off = align_up(off + (size_t)r.N * 4);
         l.s = off;
         off = align_up(off + (size_t)r.N * 4);
-        // everything a sweep produces is double-buffered: the fused pass reads
-        // slot t&1 (flip of sweep t) while it writes slot (t+1)&1
+        // edge copies and link planes are double-buffered: the fused pass reads
+        // the neighbours' edge copies of sweep t (slot t&1) while it writes
+        // those of sweep t+1.  Labels and the forest have one buffer: a tile
+        // reads its own labels of sweep t before it overwrites them.
         for (int q = 0; q < 2; ++q) {
             l.edge[q] = off;
             off = align_up(off + (size_t)r.ntiles * (r.TH + r.TW) * sizeof(float2));
-            l.lab[q] = off;
-            off = align_up(off + (size_t)r.N * sizeof(uint16_t));
             l.bx[q] = off;
             off = align_up(off + words * 4);
             l.by[q] = off;
             off = align_up(off + words * 4);
-            l.bslot[q] = off;
-            off = align_up(off + nodes);
-            l.node[q] = off;
-            off = align_up(off + nodes * sizeof(unsigned long long));
-            l.cross[q] = off;
-            off = align_up(off + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
         }
+        l.lab = off;
+        off = align_up(off + (size_t)r.N * sizeof(uint16_t));
+        l.bslot = off;
+        off = align_up(off + nodes);
+        l.node = off;
+        off = align_up(off + nodes * sizeof(unsigned long long));
+        l.cross = off;
+        off = align_up(off + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
         l.ecoin = off;
         off = align_up(off + (size_t)r.ntiles * 4 * sizeof(unsigned long long));
         l.partials = off;
@@ -162,14 +164,14 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
     d.c = reinterpret_cast<float *>(A + l.c);
     d.s = reinterpret_cast<float *>(A + l.s);
     for (int q = 0; q < 2; ++q) {
-        d.lab[q] = reinterpret_cast<uint16_t *>(A + l.lab[q]);
         d.bx[q] = reinterpret_cast<uint32_t *>(A + l.bx[q]);
         d.by[q] = reinterpret_cast<uint32_t *>(A + l.by[q]);
-        d.bslot[q] = reinterpret_cast<uint8_t *>(A + l.bslot[q]);
-        d.node[q] = reinterpret_cast<unsigned long long *>(A + l.node[q]);
-        d.cross[q] = reinterpret_cast<unsigned long long *>(A + l.cross[q]);
         d.edge[q] = reinterpret_cast<float2 *>(A + l.edge[q]);
     }
+    d.lab = reinterpret_cast<uint16_t *>(A + l.lab);
+    d.bslot = reinterpret_cast<uint8_t *>(A + l.bslot);
+    d.node = reinterpret_cast<unsigned long long *>(A + l.node);
+    d.cross = reinterpret_cast<unsigned long long *>(A + l.cross);
     d.ecoin = reinterpret_cast<unsigned long long *>(A + l.ecoin);
     d.partials = reinterpret_cast<double *>(A + l.partials);
     d.partials2 = reinterpret_cast<double *>(A + l.partials2);
@@ -603,8 +605,7 @@ int xy_flatten_labels(xy_handle *h, int32_t rep, void *d_out, int32_t out_bits)
     rc = read_state(h, rep, &s);
     if (rc) return rc;
     if (s.t == 0) return fail(XY_ESTATE, "replica %d has not swept yet", rep);
-    HIPCHECK(h, xy::launch_flatten(h->d_reps, rep, (int32_t)((s.t - 1) & 1), d.N, h->plan.big_index, d_out,
-                                   out_bits, h->stream));
+    HIPCHECK(h, xy::launch_flatten(h->d_reps, rep, d.N, h->plan.big_index, d_out, out_bits, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     return XY_OK;
 }
@@ -727,11 +728,11 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     if (e != hipSuccess) return fail(XY_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
     xy::RepDesc d;
     std::memset(&d, 0, sizeof d);
+    d.lab = reinterpret_cast<uint16_t *>(mem + off_lab);
+    d.bslot = reinterpret_cast<uint8_t *>(mem + off_bslot);
+    d.node = reinterpret_cast<unsigned long long *>(mem + off_node);
+    d.cross = reinterpret_cast<unsigned long long *>(mem + off_cross);
     for (int q = 0; q < 2; ++q) {
-        d.lab[q] = reinterpret_cast<uint16_t *>(mem + off_lab);
-        d.bslot[q] = reinterpret_cast<uint8_t *>(mem + off_bslot);
-        d.node[q] = reinterpret_cast<unsigned long long *>(mem + off_node);
-        d.cross[q] = reinterpret_cast<unsigned long long *>(mem + off_cross);
         d.bx[q] = const_cast<uint32_t *>(d_bx);
         d.by[q] = const_cast<uint32_t *>(d_by);
     }
@@ -766,7 +767,7 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     lc.gtile_end = r.ntiles;
     if (e == hipSuccess) e = xy::launch_tile(lc, xy::TILE_PLANES, s);
     if (e == hipSuccess) e = xy::launch_merge(lc, false, false, s);
-    if (e == hipSuccess) e = xy::launch_flatten(d_rep, 0, 0, r.N, P.big_index, d_labels, label_bits, s);
+    if (e == hipSuccess) e = xy::launch_flatten(d_rep, 0, r.N, P.big_index, d_labels, label_bits, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(mem);
     if (e != hipSuccess) return fail(XY_EDEVICE, "labelling failed: %s", hipGetErrorString(e));

@@ -162,7 +162,9 @@ struct RepState {
     xy_obs last;             // observables after the latest sweep
 };
 
-// Labels of sweep t (slot t&1 of every double buffer below):
+// Labels of the sweep labelled last (one buffer each: a tile reads its own
+// labels of sweep t before it writes those of sweep t + 1, and nothing reads
+// the forest of sweep t once its edge coins are drawn):
 //   lab[i]   16 bits per site, tile-local: the tile-local index y*TW + x of the
 //            smallest site of i's component inside its tile, or TW*TH + s
 //            when that component touches the tile's edge, s being its slot
@@ -179,11 +181,11 @@ struct RepState {
 
 struct RepDesc {
     float *c, *s;            // spin planes, N floats each
-    uint16_t *lab[2];        // tile-local labels
-    uint32_t *bx[2], *by[2]; // active-link bit planes
-    uint8_t *bslot[2];       // edge positions -> slot
-    unsigned long long *node[2];  // boundary-component forest
-    unsigned long long *cross[2]; // links over the right / bottom tile edges
+    uint16_t *lab;           // tile-local labels
+    uint32_t *bx[2], *by[2]; // active-link bit planes of sweep t in slot t&1
+    uint8_t *bslot;          // edge positions -> slot
+    unsigned long long *node;     // boundary-component forest
+    unsigned long long *cross;    // links over the right / bottom tile edges
     unsigned long long *ecoin;    // per tile 4 words: flip coin of the cluster at every edge position
     float2 *edge[2];         // spins before sweep t in slot t&1: per tile, its first column (TH) then first row (TW)
     double *partials;        // kNumSums planes of per-tile sums: partials[k * ntiles + tile]

@@ -30,7 +30,7 @@ struct Resolved {
 
 // Per-replica byte layout inside an arena.
 struct RepLayout {
-    size_t c, s, lab[2], bx[2], by[2], bslot[2], node[2], cross[2], edge[2], ecoin, partials, partials2, fourier, end;
+    size_t c, s, lab, bx[2], by[2], bslot, node, cross, edge[2], ecoin, partials, partials2, fourier, end;
 };
 
 struct Plan {

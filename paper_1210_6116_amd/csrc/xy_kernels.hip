@@ -435,9 +435,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
     auto own = [&](int k) -> bool { return FIXED || (yb + k < TH && lane < TW); };
     XY_G float *__restrict__ cp = gmem(R.c);
     XY_G float *__restrict__ sp = gmem(R.s);
-    // the wave's own spins first: their addresses do not depend on the sweep
-    // counter, so these loads overlap its read
+    // the wave's own spins and labels first: their addresses do not depend on
+    // the sweep counter, so these loads overlap its read
     float c0[BMAX], s0[BMAX];
+    uint32_t lv[BMAX];  // labels of the flipped sweep (flip modes)
     if constexpr (MODE != M_PLANES) {
 #pragma unroll
         for (int k = 0; k < B; ++k) {
@@ -445,6 +446,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
                 const IT i = T.site(yb + k, lane);
                 c0[k] = gel(cp, i);
                 s0[k] = gel(sp, i);
+                if constexpr (MODE == M_FLIP || MODE == M_FUSED) lv[k] = gel(gmem((const uint16_t *)R.lab), i);
             }
         }
     }
@@ -465,7 +467,6 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
     const int64_t ecount = TH + TW;
 
     if constexpr (FLIP) {
-        const XY_G uint16_t *__restrict__ lab = gmem(R.lab[par]);
         const XY_G float2 *__restrict__ eg = gmem(R.edge[par]);
         const double rx = cload(&R.st->dir[par][0]), ry = cload(&R.st->dir[par][1]);
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
@@ -487,11 +488,6 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
             }
             return f || renorm;
         };
-        // labels of the wave's rows
-        uint32_t lv[BMAX];
-#pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (own(k)) lv[k] = gel(lab, T.site(yb + k, lane));
         // halo: right column and bottom row of the neighbouring tiles (spins
         // before the sweep from their edge copies, coins from their edge-position
         // coins), flipped here exactly as their owners flip them
@@ -856,13 +852,13 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
     if (p < NB) {
         const uint32_t sl = smin[proot];
         const int64_t nbase = lt * NB;
-        gmem(R.bslot[pb])[nbase + p] = (uint8_t)sl;
+        gmem(R.bslot)[nbase + p] = (uint8_t)sl;
         if (sl == (uint32_t)p)
-            gmem(R.node[pb])[nbase + p] =
+            gmem(R.node)[nbase + p] =
                 ((unsigned long long)(uint32_t)T.site_of_local((int)proot) << 32) | (uint32_t)(nbase + p);
     }
     // 5) tile-local labels, and the links over the right and bottom edges
-    XY_G uint16_t *labn = gmem(R.lab[pb]);
+    XY_G uint16_t *labn = gmem(R.lab);
 #pragma unroll
     for (int k = 0; k < B; ++k) {
         if (own(k)) {
@@ -874,7 +870,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
         const bool xr = lane < TH && ((bxm[lane] >> (TW - 1)) & 1ull);
         const uint64_t xm = __ballot(xr);
         if (lane == 0) {
-            XY_G unsigned long long *cr = gmem(R.cross[pb]);
+            XY_G unsigned long long *cr = gmem(R.cross);
             cr[2 * lt] = xm;
             cr[2 * lt + 1] = bym[TH - 1] & twmask;
         }
@@ -925,20 +921,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
     const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
-    const uint64_t t = cload(&R.st->tl);  // the sweep whose links were labelled last
-    const int par = (int)(t & 1);
     const int NB = R.nb;
     const int nlinks = edge ? T.TW : T.TH;
     uint32_t a = 0, b = 0;
     if (lane < nlinks) {  // read with the link mask, not after it
-        const XY_G uint8_t *bsl = gmem(R.bslot[par]);
+        const XY_G uint8_t *bsl = gmem(R.bslot);
         const int64_t nt = edge ? T.down_tile() : T.right_tile();
         const int pa = edge ? T.TW + lane : 2 * T.TW + T.TH + lane;  // own bottom row / right column
         const int pn = edge ? lane : 2 * T.TW + lane;                 // neighbour's top row / left column
         a = (uint32_t)(lt * NB) + bsl[lt * NB + pa];
         b = (uint32_t)(nt * NB) + bsl[nt * NB + pn];
     }
-    const uint64_t m = gmem(R.cross[par])[2 * lt + edge];
+    const uint64_t m = gmem(R.cross)[2 * lt + edge];
     const bool on = lane < nlinks && ((m >> lane) & 1ull);
     // one union per distinct pair of the wave: the lowest lane holding a pair
     // not seen yet leads it, and every lane with the same pair drops out
@@ -950,8 +944,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
         lead = lead || lane == l;
         todo &= ~__ballot(on && a == la && b == lb);
     }
-    if (lead) union_nodes(gmem(R.node[par]), a, b);
-    if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, t + 1);
+    if (lead) union_nodes(gmem(R.node), a, b);
+    // mirror direction of the sweep after the one labelled last
+    if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, R.st->tl + 1);
 }
 
 // ------------------------------------------------- coins of edge positions
@@ -988,11 +983,9 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
     if (gtile >= gtile_end) return;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
-    const uint64_t t = cload(&R.st->tl);
-    const int par = (int)(t & 1);
     const int NB = R.nb;
-    const XY_G uint8_t *bs = gmem(R.bslot[par]) + lt * NB;
-    const XY_G unsigned long long *P = gmem(R.node[par]);
+    const XY_G uint8_t *bs = gmem(R.bslot) + lt * NB;
+    const XY_G unsigned long long *P = gmem(R.node);
     uint32_t sl[G], n[G];
     unsigned long long e[G];
     bool used[G];
@@ -1022,6 +1015,7 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
             }
         }
     }
+    const uint64_t t = cload(&R.st->tl);  // the sweep labelled last
     uint64_t cm[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) cm[g] = __ballot(used[g] && coin_of(R, (uint32_t)t, (uint32_t)(e[g] >> 32)));
@@ -1194,11 +1188,11 @@ __global__ __launch_bounds__(kThreads) void k_measure(const RepDesc *__restrict_
 }
 
 // ------------------------------------------------- canonical labels
-// Label of every site of replica r from slot q: the smallest site of its
+// Label of every site of replica r (sweep labelled last): the smallest site of its
 // cluster (tile-local root, or the key of its boundary node's root).
 template <typename IT>
-__global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict__ reps, int32_t r, int32_t q,
-                                                       void *out, int32_t out_bits)
+__global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict__ reps, int32_t r, void *out,
+                                                       int32_t out_bits)
 {
     const RepDesc &R = reps[r];
     const int64_t stride = (int64_t)gridDim.x * kThreads;
@@ -1206,11 +1200,11 @@ __global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict_
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < R.N; i += stride) {
         const IT y = (IT)i >> R.log2L, x = (IT)i & (IT)(R.L - 1);
         const int64_t lt = (int64_t)(y >> log2TH) * R.ntx + (int64_t)(x >> R.log2TW);
-        const uint32_t l = gmem(R.lab[q])[i];
+        const uint32_t l = gmem(R.lab)[i];
         const uint32_t nsite = (uint32_t)R.TH << R.log2TW;
         uint64_t key;
         if (l >= nsite) {
-            key = root_key(gmem(R.node[q]), (uint32_t)(lt * R.nb) + (l - nsite));
+            key = root_key(gmem(R.node), (uint32_t)(lt * R.nb) + (l - nsite));
         } else {
             const Tile<IT> T = make_tile<IT>(R, lt);
             key = (uint64_t)T.site_of_local((int)l);
@@ -1343,16 +1337,16 @@ hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &
     return hipGetLastError();
 }
 
-hipError_t launch_flatten(const RepDesc *d_reps, int32_t r, int32_t slot, int64_t N, bool big_index, void *d_out,
+hipError_t launch_flatten(const RepDesc *d_reps, int32_t r, int64_t N, bool big_index, void *d_out,
                           int32_t out_bits, hipStream_t s)
 {
     const int64_t blocks = std::min<int64_t>((N + kThreads - 1) / kThreads, kMaxStrideBlocks);
     if (big_index)
-        hipLaunchKernelGGL((k_flatten<uint64_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, slot,
-                           d_out, out_bits);
+        hipLaunchKernelGGL((k_flatten<uint64_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, d_out,
+                           out_bits);
     else
-        hipLaunchKernelGGL((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, slot,
-                           d_out, out_bits);
+        hipLaunchKernelGGL((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, d_out,
+                           out_bits);
     return hipGetLastError();
 }
 

@@ -54,9 +54,9 @@ hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s);
 hipError_t launch_measure(const Launch &lc, hipStream_t s);
 hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out,
                            hipStream_t s);
-// Canonical labels (smallest site of each cluster) of replica r from label slot
-// `slot`, as N values of out_bits (32 or 64) into d_out.
-hipError_t launch_flatten(const RepDesc *d_reps, int32_t r, int32_t slot, int64_t N, bool big_index, void *d_out,
+// Canonical labels (smallest site of each cluster) of replica r, of the sweep
+// labelled last, as N values of out_bits (32 or 64) into d_out.
+hipError_t launch_flatten(const RepDesc *d_reps, int32_t r, int64_t N, bool big_index, void *d_out,
                           int32_t out_bits, hipStream_t s);
 size_t lds_bytes_tile(int TH);
 
