@@ -836,17 +836,35 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
     // 3) tile-local roots of the wave's sites, and of every edge position
     //    (one thread each) with the smallest edge position per root: the
     //    slot of a component that reaches the tile's edge
-    uint32_t lr[BMAX];
-#pragma unroll
-    for (int k = 0; k < B; ++k)
-        if (own(k)) lr[k] = find_lds(lab_s, (uint32_t)((yb + k) * TW + lane));
+    //    Nothing is united any more, so the walks only read, and the rows'
+    //    walks advance together (their loads of one step are issued at once).
     const int NB = R.nb;
     const int p = threadIdx.x;  // NB <= 256 edge positions
-    uint32_t proot = 0;
-    if (p < NB) {
-        proot = find_lds(lab_s, (uint32_t)T.edge_local(p));
-        atomicMin(&smin[proot], (uint32_t)p);
+    uint32_t lr[BMAX], nx[BMAX];
+    uint32_t proot = p < NB ? lds_load(&lab_s[T.edge_local(p)]) : 0u;
+#pragma unroll
+    for (int k = 0; k < B; ++k) lr[k] = own(k) ? lds_load(&lab_s[(yb + k) * TW + lane]) : 0u;
+    uint32_t pnx = lds_load(&lab_s[proot]);
+#pragma unroll
+    for (int k = 0; k < B; ++k) nx[k] = lds_load(&lab_s[lr[k]]);
+    while (true) {
+        bool more = pnx != proot;
+#pragma unroll
+        for (int k = 0; k < B; ++k) more = more || nx[k] != lr[k];
+        if (!more) break;
+        if (pnx != proot) {
+            proot = pnx;
+            pnx = lds_load(&lab_s[proot]);
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (nx[k] != lr[k]) {
+                lr[k] = nx[k];
+                nx[k] = lds_load(&lab_s[lr[k]]);
+            }
+        }
     }
+    if (p < NB) atomicMin(&smin[proot], (uint32_t)p);
     __syncthreads();
     // 4) edge slots and boundary nodes of the tile
     if (p < NB) {
