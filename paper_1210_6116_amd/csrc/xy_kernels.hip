@@ -401,16 +401,16 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
 
 // ----------------------------------------------------------- the tile kernel
 // LDS: spin[(TH+1)*(TW+1)] float2 (tile + right halo column + bottom halo row;
-//        reused for the smallest edge position of every tile-local root)
+//        after the link pass reused for lab[TW*TH] u32, the tile-local
+//        union-find of the labelling, and the waves' column sums)
 //      | bxm[TH], bym[TH] u64 row masks of active links
-//      | scoin[4], rcoin[TH] u64 flip coins of edge positions and of rows
-//      | lab[TW*TH] u32 tile-local union-find (labelling)
+//      | rcoin[TH], scoin[4] u64 flip coins of rows and of edge positions
 // BT = rows per wave known at compile time (tiles of 64 x NW*BT for NW waves;
 // every loop over a wave's rows is unrolled and its independent loads are
 // issued together); BT = 0 is the general path (4 waves) for lattices
 // narrower than 64 and for batches of mixed tile shapes.
 template <typename IT, int MODE, int BT, int NW>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) void k_tile(const RepDesc *__restrict__ reps,
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(IT) == 4 ? 7 : 6))) void k_tile(const RepDesc *__restrict__ reps,
                                                     const uint32_t *__restrict__ tile_rep,
                                                     int32_t nrep, int64_t gtile0)
 {
@@ -455,15 +455,15 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
     const uint64_t tb = MODE == M_FUSED ? t + 1 : t;  // sweep whose links this launch activates
     const int pb = (int)(tb & 1);
 
-    // spin area: the spins with their halo; after the link pass the edge-slot
-    // table and the waves' column sums
+    // spin area: the spins with their halo; after the link pass the labelling's
+    // union-find and the waves' column sums
     float2 *spin = (float2 *)smem;
     const int sarea = max((TH + 1) * SS * (int)sizeof(float2), TW * TH * (int)sizeof(uint32_t) + NT * 16);
     uint64_t *bxm = (uint64_t *)(smem + sarea);
     uint64_t *bym = bxm + TH;
     uint64_t *rcoin = bym + TH;   // TH words: coins of the tile's rows
     uint64_t *scoin = rcoin + TH; // 4 words: coins of the edge positions
-    uint32_t *lab_s = (uint32_t *)(scoin + 4);
+    uint32_t *lab_s = (uint32_t *)smem;  // after the link pass
     const int64_t ecount = TH + TW;
 
     if constexpr (FLIP) {
@@ -733,10 +733,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
 
     __syncthreads();
     if constexpr (FLIP) fold_link_sums();
-    // smallest edge position per tile-local root, in the spin area (free now)
-    uint32_t *smin = (uint32_t *)smem;
     const uint32_t NONE = 0xFFFFFFFFu;
-    for (int q = threadIdx.x; q < TW * TH; q += NT) smin[q] = NONE;
     if constexpr (BONDS) {
         // active-link bit planes of sweep tb
         XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
@@ -864,24 +861,35 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(6))) vo
             }
         }
     }
-    if (p < NB) atomicMin(&smin[proot], (uint32_t)p);
+    // the smallest edge position of a root is marked in the root's own entry
+    // (kMark | 255 - p, so the largest mark wins), once every walk is done
+    constexpr uint32_t kMark = 0x80000000u;
+    auto slot_of = [&](uint32_t root) -> uint32_t {
+        const uint32_t m = lab_s[root];
+        return m >= kMark ? 255u - (m & 0xFFu) : NONE;
+    };
+    __syncthreads();
+    if (p < NB) atomicMax(&lab_s[proot], kMark | (255u - (uint32_t)p));
     __syncthreads();
     // 4) edge slots and boundary nodes of the tile
     if (p < NB) {
-        const uint32_t sl = smin[proot];
+        const uint32_t sl = slot_of(proot);
         const int64_t nbase = lt * NB;
         gmem(R.bslot)[nbase + p] = (uint8_t)sl;
         if (sl == (uint32_t)p)
             gmem(R.node)[nbase + p] =
                 ((unsigned long long)(uint32_t)T.site_of_local((int)proot) << 32) | (uint32_t)(nbase + p);
     }
-    // 5) tile-local labels, and the links over the right and bottom edges
+    // 5) tile-local labels, and the links over the right and bottom edges.
+    //    The lane index is taken afresh (mbcnt) so that the site offsets of
+    //    the first loads need not stay live through the kernel.
     XY_G uint16_t *labn = gmem(R.lab);
+    const int lane2 = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 #pragma unroll
     for (int k = 0; k < B; ++k) {
         if (own(k)) {
-            const uint32_t sl = smin[lr[k]];
-            gel(labn, T.site(yb + k, lane)) = (uint16_t)(sl != NONE ? (uint32_t)(TW * TH) + sl : lr[k]);
+            const uint32_t sl = slot_of(lr[k]);
+            gel(labn, T.site(yb + k, lane2)) = (uint16_t)(sl != NONE ? (uint32_t)(TW * TH) + sl : lr[k]);
         }
     }
     if (wave == 0) {
@@ -1237,11 +1245,11 @@ __global__ __launch_bounds__(kThreads) void k_flatten(const RepDesc *__restrict_
 // ====================================================== host-side launchers
 size_t lds_bytes_tile(int TH)
 {
-    // spin area: the spins with their halo, later the edge-slot table and the
-    // column sums of the waves (8 waves for 64-row tiles, else 4)
+    // spin area: the spins with their halo, later the labelling's union-find
+    // and the column sums of the waves (8 waves for 64-row tiles, else 4)
     const size_t spins = (size_t)(TH + 1) * 65 * sizeof(float2);
     const size_t later = (size_t)64 * TH * sizeof(uint32_t) + (size_t)(TH >= 64 ? 8 : 4) * 64 * 2 * sizeof(double);
-    return std::max(spins, later) + (size_t)(3 * TH + 4) * sizeof(uint64_t) + (size_t)64 * TH * sizeof(uint32_t);
+    return std::max(spins, later) + (size_t)(3 * TH + 4) * sizeof(uint64_t);
 }
 
 // Element-wise kernels over N sites loop with a grid stride: a dispatch holds
