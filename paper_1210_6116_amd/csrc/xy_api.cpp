@@ -102,6 +102,8 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         r.nty = (int32_t)(r.L / r.TH);
         r.nb = 2 * (r.TW + r.TH);
         r.ntiles = (int64_t)r.ntx * r.nty;
+        r.fin_chunks = (int32_t)((r.ntiles + xy::kFinSpan - 1) / xy::kFinSpan);
+        P.total_fin += r.fin_chunks;
         P.max_th = std::max(P.max_th, r.TH);
         P.uniform_tw = (P.uniform_tw < 0 || P.uniform_tw == r.TW) ? r.TW : 0;
         P.uniform_th = (P.uniform_th < 0 || P.uniform_th == r.TH) ? r.TH : 0;
@@ -138,7 +140,7 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         l.partials = off;
         off = align_up(off + (size_t)r.ntiles * xy::kNumSums * sizeof(double));
         l.partials2 = off;
-        off = align_up(off + (size_t)xy::kFinChunks * xy::kNumSums * sizeof(double));
+        off = align_up(off + (size_t)r.fin_chunks * xy::kNumSums * sizeof(double));
         l.fourier = off;
         off = align_up(off + (size_t)r.L * 2 * sizeof(double));
         l.end = off;
@@ -149,6 +151,8 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
     off = align_up(off + n * sizeof(xy::RepState));
     P.off_tile_rep = off;
     if (n > 1) off = align_up(off + (size_t)P.total_tiles * sizeof(uint32_t));
+    P.off_fin_rep = off;
+    if (n > 1) off = align_up(off + (size_t)P.total_fin * sizeof(uint32_t));
     P.off_obs = off;
     off = align_up(off + (size_t)(2 * kTraceChunk + 1) * n * sizeof(xy_obs));
     P.total = off;
@@ -156,7 +160,7 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
 }
 
 void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepState *st, int64_t tile_base,
-               int32_t idx, xy::RepDesc &d)
+               int64_t fin_base, int32_t idx, xy::RepDesc &d)
 {
     const Resolved &r = P.res[k];
     const RepLayout &l = P.lay[k];
@@ -190,6 +194,8 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
     d.ntx = r.ntx;
     d.nty = r.nty;
     d.nb = r.nb;
+    d.fin_chunks = r.fin_chunks;
+    d.fin_base = fin_base;
     d.idx = idx;
 }
 
@@ -207,6 +213,7 @@ struct xy_handle {
     xy::RepDesc *d_reps = nullptr;
     xy::RepState *d_state = nullptr;
     uint32_t *d_tile_rep = nullptr;
+    uint32_t *d_fin_rep = nullptr;
     xy_obs *d_trace = nullptr, *d_wmean = nullptr, *d_meas = nullptr;
     bool poisoned = false;
     // timing
@@ -259,6 +266,8 @@ xy::Launch launch_all(xy_handle *h)
     lc.uniform_th = h->plan.uniform_th;
     lc.gtile0 = 0;
     lc.gtile_end = h->plan.total_tiles;
+    lc.fin_rep = h->d_fin_rep;
+    lc.nfin = h->plan.total_fin;
     return lc;
 }
 
@@ -405,28 +414,35 @@ int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_
     h->d_reps = reinterpret_cast<xy::RepDesc *>(A + P.off_reps);
     h->d_state = reinterpret_cast<xy::RepState *>(A + P.off_state);
     h->d_tile_rep = n > 1 ? reinterpret_cast<uint32_t *>(A + P.off_tile_rep) : nullptr;
+    h->d_fin_rep = n > 1 ? reinterpret_cast<uint32_t *>(A + P.off_fin_rep) : nullptr;
     h->d_trace = reinterpret_cast<xy_obs *>(A + P.off_obs);
     h->d_wmean = h->d_trace + kTraceChunk * n;
     h->d_meas = h->d_wmean + kTraceChunk * n;
     h->reps.resize(n);
     std::vector<xy::RepState> states(n);
-    std::vector<uint32_t> tile_rep;
+    std::vector<uint32_t> tile_rep, fin_rep;
     if (n > 1) tile_rep.resize(P.total_tiles);
-    int64_t base = 0;
+    if (n > 1) fin_rep.resize(P.total_fin);
+    int64_t base = 0, fbase = 0;
     for (int32_t k = 0; k < n; ++k) {
         const Resolved &r = P.res[k];
-        fill_desc(P, k, p[k], A, h->d_state + k, base, k, h->reps[k]);
+        fill_desc(P, k, p[k], A, h->d_state + k, base, fbase, k, h->reps[k]);
         for (int64_t tt = 0; tt < r.ntiles && n > 1; ++tt) tile_rep[base + tt] = (uint32_t)k;
+        for (int64_t c = 0; c < r.fin_chunks && n > 1; ++c) fin_rep[fbase + c] = (uint32_t)k;
         base += r.ntiles;
+        fbase += r.fin_chunks;
         xy::RepState &s = states[k];
         std::memset(&s, 0, sizeof s);
         s.beta = p[k].beta;
     }
     HIPCHECK(h, hipMemcpy(h->d_reps, h->reps.data(), n * sizeof(xy::RepDesc), hipMemcpyHostToDevice));
     HIPCHECK(h, hipMemcpy(h->d_state, states.data(), n * sizeof(xy::RepState), hipMemcpyHostToDevice));
-    if (n > 1)
+    if (n > 1) {
         HIPCHECK(h, hipMemcpy(h->d_tile_rep, tile_rep.data(), tile_rep.size() * sizeof(uint32_t),
                               hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy(h->d_fin_rep, fin_rep.data(), fin_rep.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice));
+    }
     for (int32_t k = 0; k < n; ++k) {
         HIPCHECK(h, xy::launch_init_spins(h->d_reps, k, P.res[k].N, p[k].start, h->stream));
         HIPCHECK(h, xy::launch_init_fourier(h->d_reps, k, P.res[k].L, h->stream));
@@ -517,7 +533,7 @@ int xy_measure(xy_handle *h, xy_obs *out)
     if (!out) return fail(XY_EINVAL, "out pointer is NULL");
     const xy::Launch lc = launch_all(h);
     HIPCHECK(h, xy::launch_measure(lc, h->stream));
-    HIPCHECK(h, xy::launch_finalize(h->d_reps, h->plan.n, no_pcc(h), h->d_meas, h->stream));
+    HIPCHECK(h, xy::launch_finalize(lc, no_pcc(h), h->d_meas, h->stream));
     HIPCHECK(h, hipMemcpyAsync(out, h->d_meas, h->plan.n * sizeof(xy_obs), hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     return XY_OK;
@@ -765,6 +781,8 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     lc.uniform_th = P.uniform_th;
     lc.gtile0 = 0;
     lc.gtile_end = r.ntiles;
+    lc.fin_rep = nullptr;
+    lc.nfin = 0;  // no finalisation here
     if (e == hipSuccess) e = xy::launch_tile(lc, xy::TILE_PLANES, s);
     if (e == hipSuccess) e = xy::launch_merge(lc, false, false, s);
     if (e == hipSuccess) e = xy::launch_flatten(d_rep, 0, r.N, P.big_index, d_labels, label_bits, s);

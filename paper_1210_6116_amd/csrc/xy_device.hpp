@@ -144,7 +144,7 @@ __device__ __forceinline__ double unif64(uint32_t w) { return (double)w * (1.0 /
 // Scx, Ssx, Scy, Ssy, sum cos, sum sin, then the Fourier sums at k = 2 pi / L
 // along x: sum cos e^{ikx} (real, imaginary), sum sin e^{ikx} (real, imaginary)
 constexpr int kNumSums = 10;
-constexpr int kFinChunks = 8; // chunks of the two-stage (deferred) finalisation
+constexpr int64_t kFinSpan = 1024;  // tiles per chunk of the two-stage finalisation
 
 struct RepState {
     double beta;
@@ -152,7 +152,8 @@ struct RepState {
     uint64_t tl;             // the sweep whose links were activated and labelled last
     double dir[2][2];        // mirror direction of sweep t in slot t&1
     unsigned long long ties[2];  // near ties of sweep t in slot t&1
-    uint64_t pad0;
+    uint32_t fin_done;       // chunks finalised in the running finalisation launch
+    uint32_t pad0;
     double acc[9];           // PCC window sums: E, m2, ex, sx, ey, sy, ups_x, N sx^2, mk2
     int64_t acc_n;           // sweeps in the running window
     int64_t pcc_k;           // PCC steps taken (halving schedule)
@@ -189,7 +190,7 @@ struct RepDesc {
     unsigned long long *ecoin;    // per tile 4 words: flip coin of the cluster at every edge position
     float2 *edge[2];         // spins before sweep t in slot t&1: per tile, its first column (TH) then first row (TW)
     double *partials;        // kNumSums planes of per-tile sums: partials[k * ntiles + tile]
-    double *partials2;       // chunk sums of the partials (deferred finalisation), kFinChunks x kNumSums
+    double *partials2;       // chunk sums of the partials, fin_chunks x kNumSums
     double *fourier;         // cos(2 pi x / L), sin(2 pi x / L) at [2x], [2x+1], x = 0 .. L-1
     RepState *st;
     int64_t L, N;
@@ -198,6 +199,8 @@ struct RepDesc {
     uint32_t rep;
     int32_t log2L, TW, TH, log2TW, ntx, nty;
     int32_t nb;              // edge positions (and slots) per tile, 2 * (TW + TH)
+    int32_t fin_chunks;      // chunks of kFinSpan tiles (finalisation)
+    int64_t fin_base;        // global index of the replica's first chunk in its launch
     int32_t idx;             // position of the replica in its handle
 };
 

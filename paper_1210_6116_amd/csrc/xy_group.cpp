@@ -87,6 +87,7 @@ struct xy_group {
     // device tables of the running replicas (rebuilt when the set changes)
     xy::RepDesc *d_reps = nullptr;
     uint32_t *d_tile_rep = nullptr;
+    uint32_t *d_fin_rep = nullptr;  // replica of every finalisation chunk (at most one per tile)
     int64_t tile_cap = 0;
     std::vector<int32_t> order;  // running slot ids in descriptor order
     xy::Launch lc{};
@@ -128,8 +129,8 @@ int rebuild(xy_group *g)
 {
     g->order.clear();
     std::vector<xy::RepDesc> descs;
-    std::vector<uint32_t> tile_rep;
-    int64_t base = 0;
+    std::vector<uint32_t> tile_rep, fin_rep;
+    int64_t base = 0, fbase = 0;
     int32_t max_th = 1, utw = -1, uth = -1;
     for (int32_t s = 0; s < (int32_t)g->slots.size(); ++s) {
         Slot &sl = g->slots[s];
@@ -137,11 +138,13 @@ int rebuild(xy_group *g)
         const int32_t k = (int32_t)g->order.size();
         g->order.push_back(s);
         xy::RepDesc d;
-        fill_desc(sl.plan, 0, sl.p, g->mem + sl.off, sl.st, base, k, d);
+        fill_desc(sl.plan, 0, sl.p, g->mem + sl.off, sl.st, base, fbase, k, d);
         descs.push_back(d);
         const Resolved &r = sl.plan.res[0];
         for (int64_t t = 0; t < r.ntiles; ++t) tile_rep.push_back((uint32_t)k);
+        for (int64_t c = 0; c < r.fin_chunks; ++c) fin_rep.push_back((uint32_t)k);
         base += r.ntiles;
+        fbase += r.fin_chunks;
         max_th = std::max(max_th, r.TH);
         utw = (utw < 0 || utw == r.TW) ? r.TW : 0;
         uth = (uth < 0 || uth == r.TH) ? r.TH : 0;
@@ -152,6 +155,8 @@ int rebuild(xy_group *g)
     if (n) {
         GCHECK(g, hipMemcpy(g->d_reps, descs.data(), n * sizeof(xy::RepDesc), hipMemcpyHostToDevice));
         GCHECK(g, hipMemcpy(g->d_tile_rep, tile_rep.data(), tile_rep.size() * sizeof(uint32_t),
+                            hipMemcpyHostToDevice));
+        GCHECK(g, hipMemcpy(g->d_fin_rep, fin_rep.data(), fin_rep.size() * sizeof(uint32_t),
                             hipMemcpyHostToDevice));
     }
     xy::Launch &lc = g->lc;
@@ -165,6 +170,8 @@ int rebuild(xy_group *g)
     lc.uniform_th = uth;
     lc.gtile0 = 0;
     lc.gtile_end = base;
+    lc.fin_rep = g->d_fin_rep;
+    lc.nfin = fbase;
     for (int32_t k = 0; k < n; ++k) {
         Slot &sl = g->slots[g->order[k]];
         if (!sl.needs_init) continue;
@@ -207,7 +214,7 @@ int xy_group_create(size_t budget_bytes, int32_t max_slots, const xy_pcc *c, voi
     g->slots.resize(max_slots);
     // smallest tiles hold 64 x 16 sites and a site needs at least 8 bytes
     g->tile_cap = (int64_t)(budget_bytes / (64 * 16 * 8)) + max_slots;
-    const size_t tables = align_up(max_slots * sizeof(xy::RepDesc)) + align_up(g->tile_cap * sizeof(uint32_t));
+    const size_t tables = align_up(max_slots * sizeof(xy::RepDesc)) + 2 * align_up(g->tile_cap * sizeof(uint32_t));
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, budget_bytes + tables);
     if (e != hipSuccess) {
@@ -219,6 +226,7 @@ int xy_group_create(size_t budget_bytes, int32_t max_slots, const xy_pcc *c, voi
     g->arena.init(budget_bytes);
     g->d_reps = reinterpret_cast<xy::RepDesc *>(g->mem + budget_bytes);
     g->d_tile_rep = reinterpret_cast<uint32_t *>(g->mem + budget_bytes + align_up(max_slots * sizeof(xy::RepDesc)));
+    g->d_fin_rep = g->d_tile_rep + align_up(g->tile_cap * sizeof(uint32_t)) / sizeof(uint32_t);
     if (hip_stream) {
         g->stream = static_cast<hipStream_t>(hip_stream);
     } else {

@@ -26,6 +26,7 @@ struct Resolved {
     int64_t L, N;
     int32_t TW, TH, ntx, nty, nb;
     int64_t ntiles;
+    int32_t fin_chunks;  // finalisation chunks, ceil(ntiles / kFinSpan)
 };
 
 // Per-replica byte layout inside an arena.
@@ -38,15 +39,15 @@ struct Plan {
     bool big_index = false;
     std::vector<Resolved> res;
     std::vector<RepLayout> lay;
-    size_t off_reps = 0, off_state = 0, off_tile_rep = 0, off_obs = 0, total = 0;
-    int64_t total_tiles = 0;
+    size_t off_reps = 0, off_state = 0, off_tile_rep = 0, off_fin_rep = 0, off_obs = 0, total = 0;
+    int64_t total_tiles = 0, total_fin = 0;
 };
 
 int check_params(const xy_params *p, int32_t n);
 int make_plan(const xy_params *p, int32_t n, Plan &P);
 // Descriptor of replica k of plan P whose buffers start at base (layout P.lay[k]).
 void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *base, xy::RepState *st, int64_t tile_base,
-               int32_t idx, xy::RepDesc &d);
+               int64_t fin_base, int32_t idx, xy::RepDesc &d);
 // Launch state carried from one sweep to the next inside a sequence.
 struct Pipe {
     bool ready = false;        // the links of the next sweep are activated and labelled
@@ -84,7 +85,7 @@ hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int
     }
     e = timer(XY_K_FLIP, [&] { return xy::launch_tile(lc, xy::TILE_FLIP, s); });
     if (e != hipSuccess) return e;
-    e = timer(XY_K_FINALIZE, [&] { return xy::launch_finalize(d_reps, nrep, fa, nullptr, s); });
+    e = timer(XY_K_FINALIZE, [&] { return xy::launch_finalize(lc, fa, nullptr, s); });
     pp.ready = false;
     return e;
 }

@@ -39,7 +39,6 @@ namespace xy {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kFinThreads = 1024;
 
 enum : int { M_BONDS = 0, M_FLIP = 1, M_FUSED = 2, M_PLANES = 3 };
 
@@ -116,7 +115,10 @@ struct BondCtx {
     unsigned long long *ties;
 };
 
-__device__ __forceinline__ float bond_proj(const BondCtx &B, float2 v) { return __builtin_fmaf(v.x, B.rxf, v.y * B.ryf); }
+__device__ __forceinline__ float bond_proj(const BondCtx &B, float2 v)
+{
+    return __builtin_fmaf(v.x, B.rxf, v.y * B.ryf);
+}
 
 // d for the link (i, j), given bai = bl a_i
 __device__ __forceinline__ float bond_margin(float bai, float aj, uint32_t w)
@@ -410,9 +412,10 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
 // issued together); BT = 0 is the general path (4 waves) for lattices
 // narrower than 64 and for batches of mixed tile shapes.
 template <typename IT, int MODE, int BT, int NW>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(IT) == 4 ? 7 : 6))) void k_tile(const RepDesc *__restrict__ reps,
-                                                    const uint32_t *__restrict__ tile_rep,
-                                                    int32_t nrep, int64_t gtile0)
+// Occupancy target: 7 waves per SIMD with 32-bit site indices (at most 72
+// VGPRs; 64 x 32 tiles take 18 KB of LDS per block), 6 with 64-bit indices.
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(IT) == 4 ? 7 : 6))) void k_tile(
+    const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, int32_t nrep, int64_t gtile0)
 {
     constexpr bool FLIP = MODE == M_FLIP || MODE == M_FUSED;
     constexpr bool BONDS = MODE == M_BONDS || MODE == M_FUSED;
@@ -809,7 +812,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
         if (k > 0) {
             // a lane whose label above differs from its run's records their
             // union, unless its left neighbour in the run offers the same label
-            const uint32_t cleft = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE, (int)c2, 0x138, 0xf, 0xf, false);  // wave_shr:1
+            const uint32_t cleft =
+                (uint32_t)__builtin_amdgcn_update_dpp((int)NONE, (int)c2, 0x138, 0xf, 0xf, false);  // wave_shr:1
             const uint64_t need = up & __ballot(c2 != lab) & ~((xm << 1) & __ballot(cleft == c2));
             if (lane_select(need, 1u, 0u)) union_lds(lab_s, c2, lab);
         }
@@ -909,34 +913,27 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
 // components, once per distinct pair of nodes in the wave.  Reads
 // are contiguous (the edge's link mask and the two rows of edge slots); the
 // unions touch only the forest of boundary nodes.
-template <int NT>
-__device__ void sum_partials(const RepDesc &R, int64_t j0, int64_t j1, double (&tot)[kNumSums], double *red);
 __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, const double (&tot)[kNumSums]);
 
-// Deferred finalisation of a fused flip, in two stages on two kernels that
-// run anyway: kFinChunks blocks per replica beside the unions sum the tile
-// partials in chunks; one block per replica beside the edge coins sums the
-// chunks (fixed order) and finishes the sweep.
+// Finalisation of a sweep in two stages, the same arithmetic on every path:
+// (1) one block per chunk of kFinSpan tiles sums the tiles' partials;
+// (2) one block per replica sums the chunks and finishes the sweep.  After a
+// fused flip both run beside work that runs anyway (stage 1 in the first
+// blocks of the merge, stage 2 in the first blocks of the edge coins); on its
+// own, k_finalize runs stage 1 and the last block of each replica stage 2.
+__device__ __forceinline__ void fin_chunk(const RepDesc *__restrict__ reps, const uint32_t *__restrict__ fin_rep,
+                                          int32_t nrep, int64_t b, double *red);
+__device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red);
 
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge(
-    const RepDesc *__restrict__ reps,
-                                                     const uint32_t *__restrict__ tile_rep, int32_t nrep,
-                                                     int64_t gtile0, int64_t gtile_end, int32_t next_dir,
-                                                     int64_t nfin)
+    const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, const uint32_t *__restrict__ fin_rep,
+    int32_t nrep, int64_t gtile0, int64_t gtile_end, int32_t next_dir, int64_t nfin)
 {
     // the first nfin blocks: deferred finalisation, stage 1 (chunk c of
     // replica r; first in the grid, so that they overlap the unions)
     if (blockIdx.x < nfin) {
         __shared__ double red[kWaves * kNumSums];
-        const int64_t b = blockIdx.x;
-        const RepDesc &R = reps[b / kFinChunks];
-        const int64_t c = b % kFinChunks;
-        double tot[kNumSums];
-        sum_partials<kThreads>(R, c * R.ntiles / kFinChunks, (c + 1) * R.ntiles / kFinChunks, tot, red);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int k = 0; k < kNumSums; ++k) gmem(R.partials2)[c * kNumSums + k] = tot[k];
-        }
+        fin_chunk(reps, fin_rep, nrep, blockIdx.x, red);
         return;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -990,17 +987,8 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
     // the first nfin blocks: deferred finalisation, stage 2 (the chunks of
     // replica r, then the sweep; first in the grid, to overlap the coins)
     if (blockIdx.x < nfin) {
-        if (threadIdx.x == 0) {
-            const RepDesc &R = reps[blockIdx.x];
-            double tot[kNumSums];
-#pragma unroll
-            for (int k = 0; k < kNumSums; ++k) {
-                double a = 0.0;
-                for (int c = 0; c < kFinChunks; ++c) a += gmem(R.partials2)[c * kNumSums + k];
-                tot[k] = a;
-            }
-            finish_sweep(R, fa, nullptr, tot);
-        }
+        __shared__ double red[kWaves * kNumSums];
+        fin_replica(reps[blockIdx.x], fa, nullptr, red);
         return;
     }
     constexpr int G = 4;  // groups of 64 edge positions
@@ -1163,19 +1151,55 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
     st->t = t + 1;
 }
 
-template <int NT>
-__device__ void finalize_rep(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red)
+// Stage 1: chunk b of the launch (replica fin_rep[b]) into its partials2 row.
+__device__ __forceinline__ void fin_chunk(const RepDesc *__restrict__ reps, const uint32_t *__restrict__ fin_rep,
+                                          int32_t nrep, int64_t b, double *red)
+{
+    const RepDesc &R = reps[nrep == 1 ? 0 : fin_rep[b]];
+    const int64_t c = b - R.fin_base;
+    double tot[kNumSums];
+    sum_partials<kThreads>(R, c * kFinSpan, std::min<int64_t>((c + 1) * kFinSpan, R.ntiles), tot, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kNumSums; ++k) gmem(R.partials2)[c * kNumSums + k] = tot[k];
+    }
+}
+
+// Stage 2: the chunk sums of replica R in a fixed order, then the sweep.
+__device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red)
 {
     double tot[kNumSums];
-    sum_partials<NT>(R, 0, R.ntiles, tot, red);
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) tot[k] = 0.0;
+    const XY_G double *p2 = gmem(R.partials2);
+    for (int64_t c = threadIdx.x; c < R.fin_chunks; c += kThreads) {
+#pragma unroll
+        for (int k = 0; k < kNumSums; ++k) tot[k] += p2[c * kNumSums + k];
+    }
+    block_sum<kNumSums, kWaves>(tot, red);
     if (threadIdx.x == 0) finish_sweep(R, fa, measure_out, tot);
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_finalize(const RepDesc *__restrict__ reps, FlipArgs fa,
-                                                           xy_obs *measure_out)
+// Both stages in one launch: every chunk block adds itself to its replica's
+// count after its stores (release); the block that completes the count
+// (acquire) finishes the replica and resets the count for the next launch.
+__global__ __launch_bounds__(kThreads) void k_finalize(const RepDesc *__restrict__ reps,
+                                                        const uint32_t *__restrict__ fin_rep, int32_t nrep,
+                                                        FlipArgs fa, xy_obs *measure_out)
 {
-    __shared__ double red[(kFinThreads / 64) * kNumSums];
-    finalize_rep<kFinThreads>(reps[blockIdx.x], fa, measure_out, red);
+    __shared__ double red[kWaves * kNumSums];
+    __shared__ int last;
+    fin_chunk(reps, fin_rep, nrep, blockIdx.x, red);
+    const RepDesc &R = reps[nrep == 1 ? 0 : fin_rep[blockIdx.x]];
+    if (threadIdx.x == 0) {
+        const uint32_t done = __hip_atomic_fetch_add(&R.st->fin_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = done + 1 == (uint32_t)R.fin_chunks;
+        if (last) R.st->fin_done = 0u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    fin_replica(R, fa, measure_out, red);
 }
 
 // ------------------------------------------------- measure (no update)
@@ -1327,10 +1351,10 @@ hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s
 {
     const int64_t waves = 2 * (lc.gtile_end - lc.gtile0);
     const int64_t nblk = (waves + kWaves - 1) / kWaves;
-    const int64_t nfin = fin ? (int64_t)lc.nrep * kFinChunks : 0;
+    const int64_t nfin = fin ? lc.nfin : 0;
     const dim3 grid((unsigned)(nblk + nfin)), block(kThreads);
-    hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end,
-                       (int32_t)next_dir, nfin);
+    hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.fin_rep, lc.nrep, lc.gtile0,
+                       lc.gtile_end, (int32_t)next_dir, nfin);
     return hipGetLastError();
 }
 
@@ -1356,10 +1380,10 @@ hipError_t launch_measure(const Launch &lc, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out,
-                           hipStream_t s)
+hipError_t launch_finalize(const Launch &lc, const FlipArgs &fa, xy_obs *measure_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)nrep), dim3(kFinThreads), 0, s, d_reps, fa, measure_out);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)lc.nfin), dim3(kThreads), 0, s, lc.reps, lc.fin_rep, lc.nrep, fa,
+                       measure_out);
     return hipGetLastError();
 }
 

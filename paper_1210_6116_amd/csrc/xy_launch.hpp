@@ -20,6 +20,8 @@ struct Launch {
     int32_t big_index;        // 1: 64-bit site indices (some replica has N > 2^30)
     int32_t uniform_tw, uniform_th;  // tile shape shared by every replica, or 0
     int64_t gtile0, gtile_end;
+    const uint32_t *fin_rep;  // device: replica of every finalisation chunk (unused if nrep == 1)
+    int64_t nfin;             // finalisation chunks of all replicas
 };
 
 // Modes of the tile kernel.
@@ -52,8 +54,7 @@ hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s
 // second stage of a deferred finalisation.
 hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s);
 hipError_t launch_measure(const Launch &lc, hipStream_t s);
-hipError_t launch_finalize(const RepDesc *d_reps, int32_t nrep, const FlipArgs &fa, xy_obs *measure_out,
-                           hipStream_t s);
+hipError_t launch_finalize(const Launch &lc, const FlipArgs &fa, xy_obs *measure_out, hipStream_t s);
 // Canonical labels (smallest site of each cluster) of replica r, of the sweep
 // labelled last, as N values of out_bits (32 or 64) into d_out.
 hipError_t launch_flatten(const RepDesc *d_reps, int32_t r, int64_t N, bool big_index, void *d_out,
