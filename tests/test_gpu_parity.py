@@ -201,6 +201,28 @@ def test_fused_multi_sweep_parity(L, tile_rows, bits):
     lat.close()
 
 
+@pytest.mark.parametrize("L", [64, 2048])
+def test_fused_and_single_sweeps_identical(L):
+    # the fused pass (deferred finalisation in the merge and edge-coin
+    # kernels) and one sweep per call (flip, then k_finalize) sum the same
+    # tile partials with the same two-stage arithmetic: identical traces
+    xy = _gpu()
+    print("fused vs single L=%d" % L, flush=True)
+    spec = dict(L=L, beta=1.12, seed=0x5EED + L)
+    a = xy.Lattices(spec)
+    b = xy.Lattices(spec)
+    tr_a = a.sweep(12, trace=True)
+    tr_b = np.concatenate([b.sweep(1, trace=True) for _ in range(12)])
+    assert tr_a.shape == tr_b.shape
+    for name in NAMES + ("near_ties", "sweep"):
+        assert np.array_equal(tr_a[:, 0][name], tr_b[:, 0][name]), name
+    ca, sa = a.get_state()
+    cb, sb = b.get_state()
+    assert np.array_equal(ca, cb) and np.array_equal(sa, sb)
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("L,nsweeps", [(64, 6), (256, 4)])
 def test_wide_index_path_parity(L, nsweeps, monkeypatch):
     # the 64-bit site-index kernels that lattices above 2^30 sites use
