@@ -54,6 +54,26 @@ __device__ __forceinline__ const RepDesc &rep_of(const RepDesc *__restrict__ rep
 
 __device__ __forceinline__ int band_rows(int TH) { return TH >= kWaves ? TH / kWaves : 1; }
 
+// XCD-aware order.  Blocks are dispatched to the 8 XCDs in turn, so the blocks
+// an XCD receives (block j with j = x mod kXcds, counted from a block whose
+// index is a multiple of kXcds) take one contiguous band of the n work items
+// (tiles, or tile edges), W per block: neighbouring tiles, and the forest
+// entries they write and read, share that XCD's L2 in every kernel.  Returns
+// n for a slot past the end of its band.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_item(int64_t j, int W, int q, int64_t n)
+{
+    const int64_t per = (n + kXcds - 1) / kXcds;
+    const int64_t k = (j / kXcds) * W + q;
+    return k < per ? (j % kXcds) * per + k : n;
+}
+static int64_t xcd_blocks(int64_t n, int W)
+{
+    const int64_t per = (n + kXcds - 1) / kXcds;
+    return kXcds * ((per + W - 1) / W);
+}
+__host__ __device__ __forceinline__ int64_t xcd_pad(int64_t b) { return (b + kXcds - 1) / kXcds * kXcds; }
+
 // Point on the unit circle: a uniform point of the unit disk by rejection from
 // [-1,1]^2, scaled to unit length (only correctly rounded FP64 operations).
 __device__ void disk_point(uint64_t seed, uint32_t rep, uint32_t tag, uint32_t idx, uint32_t tword,
@@ -415,7 +435,8 @@ template <typename IT, int MODE, int BT, int NW>
 // Occupancy target: 7 waves per SIMD with 32-bit site indices (at most 72
 // VGPRs; 64 x 32 tiles take 18 KB of LDS per block), 6 with 64-bit indices.
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(IT) == 4 ? 7 : 6))) void k_tile(
-    const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, int32_t nrep, int64_t gtile0)
+    const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, int32_t nrep, int64_t gtile0,
+    int64_t gtile_end)
 {
     constexpr bool FLIP = MODE == M_FLIP || MODE == M_FUSED;
     constexpr bool BONDS = MODE == M_BONDS || MODE == M_FUSED;
@@ -427,8 +448,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     constexpr int kPairSums = 4;  // link sums: cos and sin of the x links, of the y links
     __shared__ double red[NW * kPairSums];
 
+    const int64_t gtile = gtile0 + xcd_item(blockIdx.x, 1, 0, gtile_end - gtile0);
+    if (gtile >= gtile_end) return;
     int64_t lt;
-    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
     const Tile<IT> T = make_tile<IT>(R, lt);
     const int TW = FIXED ? 64 : T.TW, TH = FIXED ? NW * BT : T.TH, SS = TW + 1;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -937,10 +960,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
         return;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t gw = (int64_t)(blockIdx.x - nfin) * kWaves + wave;
+    if (blockIdx.x < xcd_pad(nfin)) return;
+    const int64_t nw = 2 * (gtile_end - gtile0);  // tile edges
+    const int64_t gw = xcd_item(blockIdx.x - xcd_pad(nfin), kWaves, wave, nw);
+    if (gw >= nw) return;
     const int64_t gtile = gtile0 + (gw >> 1);
     const int edge = (int)(gw & 1);
-    if (gtile >= gtile_end) return;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
     const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
@@ -993,7 +1018,9 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
     }
     constexpr int G = 4;  // groups of 64 edge positions
     const int lane = threadIdx.x & 63;
-    const int64_t gtile = gtile0 + (int64_t)(blockIdx.x - nfin) * kWaves + (threadIdx.x >> 6);
+    if (blockIdx.x < xcd_pad(nfin)) return;
+    const int64_t gtile =
+        gtile0 + xcd_item(blockIdx.x - xcd_pad(nfin), kWaves, threadIdx.x >> 6, gtile_end - gtile0);
     if (gtile >= gtile_end) return;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
@@ -1310,13 +1337,13 @@ template <int MODE, int BT, int NW>
 static void tile_dispatch_bt(const Launch &lc, hipStream_t s)
 {
     const size_t lds = lds_bytes_tile(lc.max_th);
-    const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(NW * 64);
+    const dim3 grid((unsigned)xcd_blocks(lc.gtile_end - lc.gtile0, 1)), block(NW * 64);
     if (lc.big_index)
         hipLaunchKernelGGL((k_tile<uint64_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
-                           lc.gtile0);
+                           lc.gtile0, lc.gtile_end);
     else
         hipLaunchKernelGGL((k_tile<uint32_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
-                           lc.gtile0);
+                           lc.gtile0, lc.gtile_end);
 }
 
 // Fixed-size tiles of 64 columns when every replica of the launch has that
@@ -1349,10 +1376,9 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
 
 hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s)
 {
-    const int64_t waves = 2 * (lc.gtile_end - lc.gtile0);
-    const int64_t nblk = (waves + kWaves - 1) / kWaves;
+    const int64_t nblk = xcd_blocks(2 * (lc.gtile_end - lc.gtile0), kWaves);  // one wave per tile edge
     const int64_t nfin = fin ? lc.nfin : 0;
-    const dim3 grid((unsigned)(nblk + nfin)), block(kThreads);
+    const dim3 grid((unsigned)(xcd_pad(nfin) + nblk)), block(kThreads);
     hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.fin_rep, lc.nrep, lc.gtile0,
                        lc.gtile_end, (int32_t)next_dir, nfin);
     return hipGetLastError();
@@ -1365,8 +1391,8 @@ hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s)
     if (fin) fa = *fin;
     else std::memset(&fa, 0, sizeof fa);
     const int64_t nfin = fin ? lc.nrep : 0;
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)((ntile + kWaves - 1) / kWaves + nfin)), dim3(kThreads), 0, s,
-                       lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, nfin, fa);
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(xcd_pad(nfin) + xcd_blocks(ntile, kWaves))), dim3(kThreads), 0,
+                       s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, nfin, fa);
     return hipGetLastError();
 }
 
