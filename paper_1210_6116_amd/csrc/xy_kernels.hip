@@ -461,6 +461,12 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     auto own = [&](int k) -> bool { return FIXED || (yb + k < TH && lane < TW); };
     XY_G float *__restrict__ cp = gmem(R.c);
     XY_G float *__restrict__ sp = gmem(R.s);
+    // with 64-bit site indices, per-site accesses add the tile's first site to
+    // the (scalar) base and keep the offset inside the tile (below 2^21) 32-bit
+    constexpr bool WIDE = sizeof(IT) == 8;
+    XY_G float *__restrict__ cpw = cp + (WIDE ? T.base : (IT)0);
+    XY_G float *__restrict__ spw = sp + (WIDE ? T.base : (IT)0);
+    auto woff = [&](int k, int x) -> uint32_t { return (uint32_t)((yb + k) << T.log2L) + (uint32_t)x; };
     // the wave's own spins and labels first: their addresses do not depend on
     // the sweep counter, so these loads overlap its read
     float c0[BMAX], s0[BMAX];
@@ -469,10 +475,18 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             if (own(k)) {
-                const IT i = T.site(yb + k, lane);
-                c0[k] = gel(cp, i);
-                s0[k] = gel(sp, i);
-                if constexpr (MODE == M_FLIP || MODE == M_FUSED) lv[k] = gel(gmem((const uint16_t *)R.lab), i);
+                if constexpr (WIDE) {
+                    const uint32_t i = woff(k, lane);
+                    c0[k] = gel(cpw, i);
+                    s0[k] = gel(spw, i);
+                    if constexpr (MODE == M_FLIP || MODE == M_FUSED)
+                        lv[k] = gel(gmem((const uint16_t *)R.lab) + T.base, i);
+                } else {
+                    const IT i = T.site(yb + k, lane);
+                    c0[k] = gel(cp, i);
+                    s0[k] = gel(sp, i);
+                    if constexpr (MODE == M_FLIP || MODE == M_FUSED) lv[k] = gel(gmem((const uint16_t *)R.lab), i);
+                }
             }
         }
     }
@@ -571,8 +585,13 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                 }
                 float c1, s1;
                 if (flip_one(f, c0[k], s0[k], c1, s1)) {
-                    gel(cp, i) = c1;
-                    gel(sp, i) = s1;
+                    if constexpr (WIDE) {
+                        gel(cpw, woff(k, lane)) = c1;
+                        gel(spw, woff(k, lane)) = s1;
+                    } else {
+                        gel(cp, i) = c1;
+                        gel(sp, i) = s1;
+                    }
                 }
                 spin[(yb + k) * SS + lane] = make_float2(c1, s1);
             }
@@ -916,7 +935,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     for (int k = 0; k < B; ++k) {
         if (own(k)) {
             const uint32_t sl = slot_of(lr[k]);
-            gel(labn, T.site(yb + k, lane2)) = (uint16_t)(sl != NONE ? (uint32_t)(TW * TH) + sl : lr[k]);
+            const uint16_t v = (uint16_t)(sl != NONE ? (uint32_t)(TW * TH) + sl : lr[k]);
+            if constexpr (WIDE) gel(labn + T.base, woff(k, lane2)) = v;
+            else gel(labn, T.site(yb + k, lane2)) = v;
         }
     }
     if (wave == 0) {
