@@ -233,9 +233,9 @@ struct Tile {
         return ((p - 2 * TW - TH) << log2TW) + TW - 1;
     }
     __device__ __forceinline__ IT site_of_local(int q) const { return site(q >> log2TW, q & (TW - 1)); }
-    // tiles to the right and below (periodic)
-    __device__ __forceinline__ int64_t right_tile() const { return (int64_t)ty * ntx + (tx + 1) % ntx; }
-    __device__ __forceinline__ int64_t down_tile() const { return (int64_t)((ty + 1) % nty) * ntx + tx; }
+    // tiles to the right and below (periodic; ntx and nty are powers of two)
+    __device__ __forceinline__ int64_t right_tile() const { return (int64_t)ty * ntx + ((tx + 1) & (ntx - 1)); }
+    __device__ __forceinline__ int64_t down_tile() const { return (int64_t)((ty + 1) & (nty - 1)) * ntx + tx; }
 };
 
 template <typename IT>
