@@ -28,7 +28,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-KERNELS_SRC = os.path.join(ROOT, "paper_1210_6116_amd", "csrc", "xy_kernels.hip")
+# device code of the sweep kernels: the counter file is valid only for these exact sources
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_6116_amd", "csrc", f)
+                  for f in ("xy_kernels.hip", "xy_device.hpp", "xy_launch.hpp")] + [
+                     os.path.join(ROOT, "include", "xy.h")]
 COUNTERS = os.path.join(ROOT, "profiles", "counters_L4096.json")
 
 
@@ -72,7 +75,11 @@ def percentile(xs, q):
 
 
 def kernel_source_sha() -> str:
-    return hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def traffic_from_counters(kernel: str, launches_sites: int):
