@@ -28,6 +28,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; a wave64 VALU
+# instruction occupies its SIMD for 4 cycles (= 39.3e12 lane-instructions/s)
+VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
 # device code of the sweep kernels: the counter file is valid only for these exact sources
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_6116_amd", "csrc", f)
                   for f in ("xy_kernels.hip", "xy_device.hpp", "xy_launch.hpp")] + [
@@ -95,6 +98,18 @@ def traffic_from_counters(kernel: str, launches_sites: int):
     if not k:
         return None
     return (k["fetch_kib"] + k["write_kib"]) * 1024.0 * rec.get("copy_scale", 1.0)
+
+
+def valu_from_counters(kernel: str):
+    """SQ_INSTS_VALU (wave instructions, all waves) per launch of `kernel` from
+    the committed rocprofv3 counter run, or None when missing or stale."""
+    try:
+        rec = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    return rec.get("kernels", {}).get(kernel, {}).get("valu_insts")
 
 
 def cpu_baseline(L: int, beta: float, seed: int, nsweeps: int):
@@ -261,6 +276,7 @@ def main():
     print("bench: timed %d sweeps in %.3f s" % (args.steps, dt), file=sys.stderr, flush=True)
 
     roofline = None
+    valu_issue = None
     latency = {}
     kernels = {}
     if not args.no_instrument:
@@ -288,6 +304,13 @@ def main():
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(dom, N),
                     "alg_bytes_per_launch": kd["alg_bytes"], "avg_launch_ms": kd["avg_ms"]}
+        vi = valu_from_counters(dom)
+        if vi:
+            # the same kernel against its instruction-issue ceiling
+            rate = vi * 64 / (kd["avg_ms"] * 1e-3) / 1e12
+            valu_issue = {"bound": "alu", "kernel": dom, "achieved": rate, "peak": VALU_PEAK_TLANE,
+                          "unit": "T VALU lane-instructions/s", "frac": rate / VALU_PEAK_TLANE,
+                          "valu_insts_per_launch": vi}
     lat.close()
 
     line = {
@@ -309,6 +332,7 @@ def main():
                                                                          args.warmup, args.steps),
                    "L": L, "beta": beta, "seed": seed, "parallelism": "single GPU"},
         "roofline": roofline,
+        "valu_issue": valu_issue,
         "latency": latency,
         "kernels": kernels,
     }
