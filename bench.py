@@ -169,8 +169,13 @@ def bench_batched(sweeps: int, nrep: int = 512):
     import paper_1210_6116_amd as xy
     import xyworkloads as wl
 
+    from paper_1210_6116_amd import autotune
+
     specs = wl.batched_replicas(nrep)
     total = sum(sp["L"] ** 2 for sp in specs)
+    # tile height picked by the autotuner for this replica set (timed here, not cached)
+    rows, tune_s = autotune.tune(specs, use_cache=False)
+    specs = [dict(sp, tile_rows=rows) for sp in specs]
     chunk = 10 if sweeps % 10 == 0 else 1
     stream = torch.cuda.Stream()
     bat = xy.Lattices(specs, stream=stream)
@@ -197,7 +202,8 @@ def bench_batched(sweeps: int, nrep: int = 512):
     torch.cuda.empty_cache()
     return {"workload": "%d replicas, L log-uniform over 64..2048, beta uniform on [1.0, 1.2], %d timed sweeps "
                         "each; batched = one handle replayed from a %d-sweep HIP graph; plain = one handle per "
-                        "replica, swept one after another" % (nrep, sweeps, chunk),
+                        "replica, swept one after another; both with the autotuned tile height" % (nrep, sweeps, chunk),
+            "tile_rows": rows, "autotune_ms_per_sweep": {str(k): v * 1e3 for k, v in sorted(tune_s.items())},
             "spins": total, "batched_value": sweeps * total / dt_b, "plain_value": sweeps * total / dt_p,
             "unit": "spin updates/s", "speedup": dt_p / dt_b}
 

@@ -30,6 +30,12 @@ def _key(specs, arch):
 
 def tile_rows(specs, sweeps: int = 20, warmup: int = 5, use_cache: bool = True) -> int:
     """Fastest tile height for these replicas (a list of dicts with L, beta, seed)."""
+    return tune(specs, sweeps, warmup, use_cache)[0]
+
+
+def tune(specs, sweeps: int = 20, warmup: int = 5, use_cache: bool = True):
+    """(fastest tile height, {tile height: seconds per sweep}) for these replicas;
+    the timings are those of the run that chose it (from the cache if present)."""
     from . import Lattices
 
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
@@ -42,7 +48,8 @@ def tile_rows(specs, sweeps: int = 20, warmup: int = 5, use_cache: bool = True) 
         except (OSError, ValueError):
             cache = {}
         if key in cache:
-            return int(cache[key]["tile_rows"])
+            rec = cache[key]
+            return int(rec["tile_rows"]), {int(k): v * 1e-3 for k, v in rec["ms_per_sweep"].items()}
     timings = {}
     label64 = max(int(s["L"]) for s in specs) ** 2 >= 2 ** 32
     for rows in CANDIDATES:
@@ -64,4 +71,4 @@ def tile_rows(specs, sweeps: int = 20, warmup: int = 5, use_cache: bool = True) 
         json.dump(cache, open(path, "w"), indent=1)
     except OSError:
         pass
-    return best
+    return best, timings

@@ -1,0 +1,54 @@
+"""Tile-height autotuner (paper_1210_6116_amd.autotune).
+
+The tuner times each candidate tile height on the replica set and keeps the
+fastest; the choice only changes speed, never results: links, labels and coins
+are functions of the lattice, the sweep and the canonical roots, not of the
+tiling.  Checks: the pick is a candidate with the smallest measured time, the
+cache round-trips it, and replicas swept with every candidate height end in
+bit-identical states and observables.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _specs():
+    return [dict(L=L, beta=b, seed=0xA070 + k, rep=k)
+            for k, (L, b) in enumerate([(64, 1.0), (128, 1.12), (256, 1.05), (64, 1.2), (512, 1.1)])]
+
+
+def test_autotune_pick_and_cache(tmp_path, monkeypatch):
+    from paper_1210_6116_amd import autotune
+    monkeypatch.setenv("XDG_CACHE_HOME", str(tmp_path))
+    specs = _specs()
+    best, timings = autotune.tune(specs, sweeps=5, warmup=2, use_cache=False)
+    print("autotune:", best, {k: "%.1f us" % (v * 1e6) for k, v in timings.items()}, flush=True)
+    assert set(timings) == set(autotune.CANDIDATES)
+    assert best in autotune.CANDIDATES and timings[best] == min(timings.values())
+    assert all(v > 0 for v in timings.values())
+    # the cached record gives the same pick without timing again
+    again, cached = autotune.tune(specs, use_cache=True)
+    assert again == best
+    assert cached == pytest.approx(timings)
+    assert autotune.tile_rows(specs) == best
+
+
+def test_results_do_not_depend_on_tile_height():
+    import paper_1210_6116_amd as xy
+    from paper_1210_6116_amd import autotune
+    specs = _specs()
+    runs = {}
+    for rows in autotune.CANDIDATES:
+        lat = xy.Lattices([dict(s, tile_rows=rows) for s in specs])
+        tr = lat.sweep(12, trace=True)
+        states = [lat.get_state(k) for k in range(len(specs))]
+        lat.close()
+        runs[rows] = (tr, states)
+    ref_tr, ref_states = runs[autotune.CANDIDATES[0]]
+    for rows, (tr, states) in runs.items():
+        for f in ("E", "m2", "ex", "sx", "mk2"):
+            np.testing.assert_allclose(tr[f], ref_tr[f], rtol=1e-10, atol=1e-12, err_msg="%s rows=%d" % (f, rows))
+        for k in range(len(specs)):
+            assert np.array_equal(states[k][0], ref_states[k][0]), (rows, k)
+            assert np.array_equal(states[k][1], ref_states[k][1]), (rows, k)
