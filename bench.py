@@ -142,9 +142,11 @@ def bench_l65536(sweeps: int):
     torch.cuda.synchronize()
     lat.timing(True)
     t0 = time.perf_counter()
-    lat.pcc(sweeps, 1, 0.004, dbeta_min=0.0005, halve_every=250)
+    means = lat.pcc(sweeps, 1, 0.004, dbeta_min=0.0005, halve_every=250, means=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    every = max(1, sweeps // 40)
+    beta_trace = [float(b) for b in means["beta"][every - 1::every, 0]]
     ms, n, per = lat.timing_read(sweeps)
     lat.timing(False)
     beta = lat.beta()
@@ -158,7 +160,8 @@ def bench_l65536(sweeps: int):
             "value": sweeps * L * L / dt, "unit": "spin updates/s", "ms_per_sweep": dt / sweeps * 1e3,
             "sweep_ms_p50": percentile(per, 50), "sweep_ms_p99": percentile(per, 99),
             "kernels_ms": {k: ms[i] / n[i] for i, k in enumerate(xy._lib.KERNEL_NAMES) if n[i] and k != "sweep"},
-            "beta_after": beta, "arena_GB": arena_gb, "alloc_init_s": t_alloc}
+            "beta_after": beta, "beta_trace_every": every, "beta_trace": beta_trace,
+            "arena_GB": arena_gb, "alloc_init_s": t_alloc}
 
 
 def bench_batched(sweeps: int, nrep: int = 512):
@@ -239,6 +242,8 @@ def main():
     ap.add_argument("--no-instrument", action="store_true", help="skip the instrumented pass")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the L=65536 PCC, batched and serving legs")
+    ap.add_argument("--extras", default="l65536,batched,serving",
+                    help="comma-separated subset of the extra workloads to run")
     ap.add_argument("--l65536-sweeps", type=int, default=100)
     ap.add_argument("--batched-sweeps", type=int, default=100)
     ap.add_argument("--serve-requests", type=int, default=40)
@@ -344,9 +349,12 @@ def main():
     }
     if not args.no_extras:
         extras = {}
-        for name, fn in (("L65536_pcc", lambda: bench_l65536(args.l65536_sweeps)),
-                         ("batched_vs_plain", lambda: bench_batched(args.batched_sweeps)),
-                         ("serving", lambda: bench_serving(args.serve_requests, 200, 2000))):
+        chosen = set(args.extras.split(","))
+        for key, name, fn in (("l65536", "L65536_pcc", lambda: bench_l65536(args.l65536_sweeps)),
+                              ("batched", "batched_vs_plain", lambda: bench_batched(args.batched_sweeps)),
+                              ("serving", "serving", lambda: bench_serving(args.serve_requests, 200, 2000))):
+            if key not in chosen:
+                continue
             print("bench: %s" % name, file=sys.stderr, flush=True)
             try:
                 extras[name] = fn()

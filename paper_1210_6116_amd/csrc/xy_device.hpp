@@ -71,20 +71,6 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ double uniform_f64(double v)
-{
-    return __longlong_as_double((long long)uniform_u64((uint64_t)__double_as_longlong(v)));
-}
-
-// A value computed in vector registers from scalars (there are no scalar FP
-// conversions), moved back to a scalar register.
-__device__ __forceinline__ float uniform_f32(float v)
-{
-    float r;
-    asm("v_readfirstlane_b32 %0, %1" : "=s"(r) : "v"(v));
-    return r;
-}
-
 // Element i of a global array.  With 32-bit site indices (N <= 2^30) the byte
 // offset fits 32 bits, so the access can take a scalar base and one 32-bit
 // vector offset (shared by arrays of the same element size) instead of a
