@@ -218,11 +218,18 @@ def bench_serving(n_requests: int, sweeps_lo: int, sweeps_hi: int):
     from paper_1210_6116_amd.serve import serve
 
     trace = wl.serving_trace(n_requests=n_requests, sweeps_lo=sweeps_lo, sweeps_hi=sweeps_hi)
-    res = serve(trace, budget_bytes=200 * 10 ** 9, max_slots=64, round_sweeps=16)
+    last = [0.0]
+
+    def progress(done, total, t):
+        if t - last[0] >= 20.0 or done == total:
+            last[0] = t
+            print("bench: serving %d/%d requests done at %.0f s" % (done, total, t), file=sys.stderr, flush=True)
+
+    res = serve(trace, budget_bytes=200 * 10 ** 9, max_slots=64, round_sweeps=16, progress=progress)
     s = res["summary"]
     offered = s["offered_updates"] / (max(r["arrival"] for r in trace) + 1e-9)
     return {"workload": "%d requests, Poisson rate 20/s, L = 2^(8..13), %d-%d sweeps each (the full trace has "
-                        "200 requests of 1000-10000 sweeps), PCC window 1, 200 GB budget, 64 slots"
+                        "200 requests of 1000-10000 sweeps), PCC window 1, 200 GB budget, 64 slots, FIFO admission"
                         % (n_requests, sweeps_lo, sweeps_hi),
             "served_value": s["served_updates_per_s"], "unit": "spin updates/s",
             "ttc_p50_s": s["ttc_p50_s"], "ttc_p99_s": s["ttc_p99_s"], "makespan_s": s["makespan_s"],
@@ -247,6 +254,8 @@ def main():
     ap.add_argument("--l65536-sweeps", type=int, default=100)
     ap.add_argument("--batched-sweeps", type=int, default=100)
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-sweeps-lo", type=int, default=200)
+    ap.add_argument("--serve-sweeps-hi", type=int, default=2000)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -352,7 +361,8 @@ def main():
         chosen = set(args.extras.split(","))
         for key, name, fn in (("l65536", "L65536_pcc", lambda: bench_l65536(args.l65536_sweeps)),
                               ("batched", "batched_vs_plain", lambda: bench_batched(args.batched_sweeps)),
-                              ("serving", "serving", lambda: bench_serving(args.serve_requests, 200, 2000))):
+                              ("serving", "serving", lambda: bench_serving(args.serve_requests, args.serve_sweeps_lo,
+                                                                           args.serve_sweeps_hi))):
             if key not in chosen:
                 continue
             print("bench: %s" % name, file=sys.stderr, flush=True)

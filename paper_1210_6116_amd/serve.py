@@ -62,12 +62,13 @@ class Group:
 
 
 def serve(trace, budget_bytes: int = 200 * 10 ** 9, max_slots: int = 64, pcc: xy_pcc | None = None,
-          round_sweeps: int = 16, clock=time.perf_counter, sleep=time.sleep):
+          round_sweeps: int = 16, clock=time.perf_counter, sleep=time.sleep, progress=None):
     """Runs the request trace in real time (arrival times in seconds from start).
 
     trace: list of dicts with arrival, L, sweeps, seed, beta0.  Returns a dict
     with per-request records and the summary (makespan, served updates/s,
-    p50 / p99 TTC in seconds, mean slots in use).
+    p50 / p99 TTC in seconds, mean slots in use).  progress, if given, is
+    called as progress(finished, total, seconds) whenever requests finish.
     """
     if pcc is None:
         pcc = xy_pcc(window=1, dbeta0=0.004, dbeta_min=0.0005, halve_every=250, target=PCC_TARGET)
@@ -78,6 +79,7 @@ def serve(trace, budget_bytes: int = 200 * 10 ** 9, max_slots: int = 64, pcc: xy
     nxt = 0
     t0 = clock()
     running_samples = []
+    finished = 0
     while nxt < len(order) or slot_of:
         now = clock() - t0
         # admit in arrival order while the head fits
@@ -97,12 +99,16 @@ def serve(trace, budget_bytes: int = 200 * 10 ** 9, max_slots: int = 64, pcc: xy
         running_samples.append(len(slot_of))
         grp.round(round_sweeps)
         done_t = clock() - t0
-        for slot in grp.poll():
+        polled = grp.poll()
+        for slot in polled:
             k = slot_of.pop(slot)
             last, beta, beta_mean = grp.result(slot)
             recs[k].update(finished=done_t, ttc=done_t - recs[k]["arrival"], beta=beta, beta_mean=beta_mean,
                            E=float(last["E"]), m2=float(last["m2"]))
             grp.release(slot)
+        finished += len(polled)
+        if polled and progress is not None:
+            progress(finished, len(order), done_t)
     grp.close()
     makespan = max(r["finished"] for r in recs.values()) - min(r["arrival"] for r in recs.values())
     updates = sum(r["L"] * r["L"] * r["sweeps"] for r in recs.values())
