@@ -511,7 +511,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
         const double rx = cload(&R.st->dir[par][0]), ry = cload(&R.st->dir[par][1]);
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
         const uint32_t tf = (uint32_t)t;
-        auto flip_one = [&](bool f, float c0, float s0, float &c1, float &s1) -> bool {
+        auto flip_one = [&](bool f, float c0, float s0, float &c1, float &s1) {
             c1 = c0;
             s1 = s0;
             if (f) {
@@ -526,7 +526,6 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                 c1 = (float)(c / n);
                 s1 = (float)(s / n);
             }
-            return f || renorm;
         };
         // halo: right column and bottom row of the neighbouring tiles (spins
         // before the sweep from their edge copies, coins from their edge-position
@@ -584,14 +583,15 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                                    : ((rcoin[l >> T.log2TW] >> (l & (uint32_t)(TW - 1))) & 1ull);
                 }
                 float c1, s1;
-                if (flip_one(f, c0[k], s0[k], c1, s1)) {
-                    if constexpr (WIDE) {
-                        gel(cpw, woff(k, lane)) = c1;
-                        gel(spw, woff(k, lane)) = s1;
-                    } else {
-                        gel(cp, i) = c1;
-                        gel(sp, i) = s1;
-                    }
+                // every site is stored, flipped or not: lines written in
+                // part (cluster edges) cost the memory more than whole lines
+                flip_one(f, c0[k], s0[k], c1, s1);
+                if constexpr (WIDE) {
+                    gel(cpw, woff(k, lane)) = c1;
+                    gel(spw, woff(k, lane)) = s1;
+                } else {
+                    gel(cp, i) = c1;
+                    gel(sp, i) = s1;
                 }
                 spin[(yb + k) * SS + lane] = make_float2(c1, s1);
             }
