@@ -20,7 +20,9 @@
 //                  others from the edge coins), reflection of flipped clusters
 //                  in FP64 with one rounding to the FP32 state, the ten sums of
 //                  the flipped state
-//   k_finalize     per replica: observables, PCC window and beta step, counter
+//   k_finalize     sums of the tiles' partials in chunks; the last chunk of a
+//                  replica finishes it: observables, PCC window and beta step,
+//                  sweep counter
 // k_tile<FUSED> does FLIP for sweep t and BONDS for sweep t+1 in one pass over
 // the spins (whenever beta cannot change in between); the finalisation of such
 // a flip then runs in two stages beside the next merge and edge coins.
