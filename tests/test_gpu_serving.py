@@ -16,21 +16,31 @@ NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x", "mk2")
 
 
 def test_graph_replay_equals_sweeps():
+    """Every replay of a captured 10-sweep graph equals 10 eager sweeps; eager
+    work (a measurement, host reads) and synchronisations run between the
+    replays, and the last replay's results are checked like the first's."""
     import paper_1210_6116_amd as xy
     specs = [dict(L=L, beta=1.1, seed=0x6A, rep=k) for k, L in enumerate((64, 256, 128))]
     a = xy.Lattices(specs)
     b = xy.Lattices(specs)
+    for replay in range(4):
+        a.sweep(10)
+        b.sweep_graph(10, 1)
+        for k in range(len(specs)):
+            ca, sa = a.get_state(k)
+            cb, sb = b.get_state(k)
+            assert np.array_equal(ca, cb) and np.array_equal(sa, sb), (replay, k)
+            assert np.array_equal(a.labels(k), b.labels(k)), (replay, k)
+            assert a.sweep_count(k)[0] == b.sweep_count(k)[0] == 10 * (replay + 1)
+        ma, mb = a.measure(), b.measure()
+        for name in NAMES:
+            assert np.array_equal(ma[name], mb[name]), (replay, name)
+    # several replays in one call
     a.sweep(30)
     b.sweep_graph(10, 3)
     for k in range(len(specs)):
-        ca, sa = a.get_state(k)
-        cb, sb = b.get_state(k)
-        assert np.array_equal(ca, cb) and np.array_equal(sa, sb)
+        assert np.array_equal(a.get_state(k)[0], b.get_state(k)[0])
         assert np.array_equal(a.labels(k), b.labels(k))
-        assert a.sweep_count(k)[0] == b.sweep_count(k)[0] == 30
-    ma, mb = a.measure(), b.measure()
-    for name in NAMES:
-        assert np.array_equal(ma[name], mb[name])
     a.close()
     b.close()
 
