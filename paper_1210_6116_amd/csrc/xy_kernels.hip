@@ -478,11 +478,13 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
         for (int k = 0; k < B; ++k) {
             if (own(k)) {
                 if constexpr (WIDE) {
+                    // (2^32-site lattices: each pass streams the arrays once,
+                    // past caches far smaller than them)
                     const uint32_t i = woff(k, lane);
-                    c0[k] = gel(cpw, i);
-                    s0[k] = gel(spw, i);
+                    c0[k] = __builtin_nontemporal_load(&gel(cpw, i));
+                    s0[k] = __builtin_nontemporal_load(&gel(spw, i));
                     if constexpr (MODE == M_FLIP || MODE == M_FUSED)
-                        lv[k] = gel(gmem((const uint16_t *)R.lab) + T.base, i);
+                        lv[k] = __builtin_nontemporal_load(&gel(gmem((const uint16_t *)R.lab) + T.base, i));
                 } else {
                     const IT i = T.site(yb + k, lane);
                     c0[k] = gel(cp, i);
@@ -589,8 +591,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                 // part (cluster edges) cost the memory more than whole lines
                 flip_one(f, c0[k], s0[k], c1, s1);
                 if constexpr (WIDE) {
-                    gel(cpw, woff(k, lane)) = c1;
-                    gel(spw, woff(k, lane)) = s1;
+                    // streaming stores (2^32-site lattices)
+                    __builtin_nontemporal_store(c1, &gel(cpw, woff(k, lane)));
+                    __builtin_nontemporal_store(s1, &gel(spw, woff(k, lane)));
                 } else {
                     gel(cp, i) = c1;
                     gel(sp, i) = s1;
@@ -938,7 +941,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
         if (own(k)) {
             const uint32_t sl = slot_of(lr[k]);
             const uint16_t v = (uint16_t)(sl != NONE ? (uint32_t)(TW * TH) + sl : lr[k]);
-            if constexpr (WIDE) gel(labn + T.base, woff(k, lane2)) = v;
+            if constexpr (WIDE) __builtin_nontemporal_store(v, &gel(labn + T.base, woff(k, lane2)));
             else gel(labn, T.site(yb + k, lane2)) = v;
         }
     }
