@@ -344,6 +344,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
+        # the paper's only single-GPU timing (L = 4096, 500,000 MCS with measurements in
+        # about 14 h on one GeForce GTX580): another machine, quoted as context
+        "paper_context": {"value": 4096 ** 2 * 5e5 / (14 * 3600.0), "unit": "spin updates/s",
+                          "hardware": "1 x GeForce GTX580", "ratio": value / (4096 ** 2 * 5e5 / (14 * 3600.0))},
         "dtype": "f32 state, f64 reflection and sums",
         "data": "synthetic (seeded Philox hot start)",
         "config": {"workload": "plain SW sweep, 2D XY periodic L=%d, beta=%g, uint%d canonical labels "
