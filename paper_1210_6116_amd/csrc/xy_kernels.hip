@@ -1083,9 +1083,36 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
         }
     }
     const uint64_t t = cload(&R.st->tl);  // the sweep labelled last
-    uint64_t cm[G];
+    // the used slots' keys packed in rank order into the wave's part of LDS,
+    // so that the Philox blocks of the coins run once per 64 used slots
+    // rather than once per group of 64 positions
+    __shared__ uint32_t keys_s[kWaves * G * 64];
+    uint32_t *ks = keys_s + (threadIdx.x >> 6) * (G * 64);
+    uint32_t rank[G];
+    uint32_t nused = 0;  // the same in every lane
 #pragma unroll
-    for (int g = 0; g < G; ++g) cm[g] = __ballot(used[g] && coin_of(R, (uint32_t)t, (uint32_t)(e[g] >> 32)));
+    for (int g = 0; g < G; ++g) {
+        const uint64_t bm = __ballot(used[g]);
+        rank[g] = nused + __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+        if (used[g]) ks[rank[g]] = (uint32_t)(e[g] >> 32);
+        nused += (uint32_t)__popcll(bm);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint64_t cb[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const uint32_t r = (uint32_t)(q * 64 + lane);
+        cb[q] = (uint32_t)(q * 64) < nused ? __ballot(r < nused && coin_of(R, (uint32_t)t, ks[r])) : 0ull;
+    }
+    uint64_t cm[G];  // bit l of cm[g]: the coin of used position g * 64 + l
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t q = rank[g] >> 6;
+        const uint64_t w = q == 0 ? cb[0] : q == 1 ? cb[1] : q == 2 ? cb[2] : cb[3];
+        cm[g] = __ballot(used[g] && ((w >> (rank[g] & 63u)) & 1ull));
+    }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const uint32_t q = sl[g] >> 6;
