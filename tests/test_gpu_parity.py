@@ -169,6 +169,39 @@ def test_batched_replicas_match_plain():
     batch.close()
 
 
+def test_batched_512_replicas_sampled_against_oracle():
+    # The batched workload at its full shape (512 replicas, L = 64 ... 2048, beta in
+    # [1.0, 1.2], 64-row tiles, sweeps replayed from a captured graph): replicas
+    # of every size up to 256 are checked against the oracle bit for bit
+    xy = _gpu()
+    specs = [dict(sp, tile_rows=64) for sp in wl.batched_replicas(512)]
+    picks = []
+    for L in (64, 128, 256):
+        picks += [k for k, sp in enumerate(specs) if sp["L"] == L][:2]
+    print("512-replica batch, sampled replicas %s" % picks, flush=True)
+    batch = xy.Lattices(specs)
+    nsw = 3
+    batch.sweep_graph(nsw, 1)
+    meas = batch.measure()
+    for k in picks:
+        sp = specs[k]
+        orc = oracle.Lattice(L=sp["L"], beta=sp["beta"], seed=sp["seed"], rep=sp["rep"], storage32=True)
+        for _ in range(nsw):
+            obs_o, _, _, _, lab_o = orc.sweep_detail()
+        c, s = batch.get_state(k)
+        assert np.array_equal(c.astype(np.float64), orc.c) and np.array_equal(s.astype(np.float64), orc.s), k
+        assert np.array_equal(batch.labels(k), lab_o), k
+        _check_obs(meas[k], obs_o, ("replica", k))
+        assert batch.sweep_count(k)[0] == nsw
+    # every replica: unit spins and the same sweep count
+    for k in range(0, 512, 37):
+        c, s = batch.get_state(k)
+        n2 = c.astype(np.float64) ** 2 + s.astype(np.float64) ** 2
+        assert np.max(np.abs(n2 - 1.0)) < 1e-6, k
+        assert batch.sweep_count(k)[0] == nsw
+    batch.close()
+
+
 def test_full_size_l4096_one_sweep():
     # The bench configuration (L = 4096, beta = 1.12, default tiles): one sweep
     # checked element by element against the oracle.
