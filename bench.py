@@ -261,7 +261,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the sweep on a single MI355X "
+        print("bench.py measures one GPU only: the sweep runs on a single MI355X "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
