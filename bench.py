@@ -188,6 +188,16 @@ def bench_batched(sweeps: int, nrep: int = 512):
     bat.sweep_graph(chunk, sweeps // chunk)
     torch.cuda.synchronize()
     dt_b = time.perf_counter() - t0
+    # latency of one round (one replay of the graph: `chunk` sweeps of every
+    # replica), from events on the handle's stream
+    rounds = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bat.sweep_graph(chunk, 1)
+        e1.record(stream)
+        e1.synchronize()
+        rounds.append(e0.elapsed_time(e1))
     bat.close()
     del bat
     plain = [xy.Lattices(sp, stream=stream) for sp in specs]
@@ -207,6 +217,7 @@ def bench_batched(sweeps: int, nrep: int = 512):
                         "each; batched = one handle replayed from a %d-sweep HIP graph; plain = one handle per "
                         "replica, swept one after another; both with the autotuned tile height" % (nrep, sweeps, chunk),
             "tile_rows": rows, "autotune_ms_per_sweep": {str(k): v * 1e3 for k, v in sorted(tune_s.items())},
+            "round_sweeps": chunk, "round_ms_p50": percentile(rounds, 50), "round_ms_p99": percentile(rounds, 99),
             "spins": total, "batched_value": sweeps * total / dt_b, "plain_value": sweeps * total / dt_p,
             "unit": "spin updates/s", "speedup": dt_p / dt_b}
 
