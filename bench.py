@@ -125,6 +125,30 @@ def cpu_baseline(L: int, beta: float, seed: int, nsweeps: int):
             "host_cpus": os.cpu_count()}
 
 
+def cpu_batched(specs, nsweeps: int):
+    """The oracle over every replica of the batch: one replica per task on a pool
+    of host threads (the C oracle runs outside the GIL), nsweeps sweeps each from
+    the oracle's own hot starts (the starts are inside the timed region)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+
+    def one(sp):
+        lat = oracle.Lattice(L=sp["L"], beta=sp["beta"], seed=sp["seed"], rep=sp["rep"], storage32=True)
+        lat.run(nsweeps)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(one, sorted(specs, key=lambda sp: -sp["L"])))  # largest first
+    dt = time.perf_counter() - t0
+    total = sum(sp["L"] ** 2 for sp in specs)
+    return {"value": nsweeps * total / dt, "unit": "spin updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d sweeps of all %d replicas of the batch (hot starts included), %d threads, %.1f s"
+                      % (nsweeps, len(specs), threads, dt)}
+
+
 def bench_l65536(sweeps: int):
     """Generalized-PCC run of one L = 65536 lattice (64-bit labels), beta0 = 1.0,
     window 1, dbeta 0.004 halved every 250 steps down to 0.0005."""
@@ -390,6 +414,9 @@ def main():
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)
+        bat = line.get("extras", {}).get("batched_vs_plain")
+        if bat is not None and "error" not in bat:
+            bat["cpu_baseline"] = cpu_batched(wl.batched_replicas(512), 1)
     print(json.dumps(line), flush=True)
 
 
