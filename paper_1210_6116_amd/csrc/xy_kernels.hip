@@ -1123,11 +1123,12 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
 }
 
 // ------------------------------------------------- finalise a sweep
-// One block per replica: the per-tile sums in a fixed order, the observables,
-// the PCC window / beta step, and the sweep counter.  measure_out != null:
-// observables of the current configuration only (no counters touched).
-// Besides its own kernel, it runs in extra blocks of the merge kernel of the
-// next sweep when the flip was fused with that sweep's links.
+// A replica's per-tile partials are summed in a fixed order (chunks of
+// kFinSpan tiles, then the chunks), and finish_sweep forms the observables,
+// runs the PCC window / beta step and advances the sweep counter.
+// measure_out != null: observables of the current configuration only (no
+// counters touched).
+//
 // Sums of the per-tile partials of replica R over the tiles [j0, j1), in a
 // fixed order (thread j takes tiles j0 + j, j0 + j + NT, ...); thread 0 gets
 // the totals.
