@@ -3,16 +3,19 @@
 
 Metric: spin updates per second = sweeps x L^2 / wall time.  The headline
 workload is a single L = 4096 lattice at beta = 1.12 from a uniform-angle hot
-start: `--warmup` thermalisation sweeps (default 200) are run untimed, then
-exactly `--steps` sweeps (default 1000) are timed between two device
+start: 200 thermalisation sweeps (always, untimed) and `--warmup` more untimed
+sweeps, then exactly `--steps` sweeps timed between two device
 synchronisations.  A "step" is one full sweep: mirror direction, link
 activation, labelling, cluster reflection and the observable reductions.
 
 A second, instrumented pass of the same length records HIP events on the
 handle's stream around every kernel launch and every sweep; it gives the
 per-kernel average durations (roofline of the dominant kernel) and the
-per-sweep p50 / p99 latency.  The CPU oracle is timed on a bounded sample of
-the same workload on this host (cpu_baseline).  Prints one JSON line.
+per-sweep p50 / p99 latency.  The CPU oracle is timed on 20 sweeps of the
+GPU's thermalised lattice on this host (cpu_baseline).  The other workloads
+(L = 65536 PCC run, 512-replica batch against plain handles, the serving
+trace against one-request-at-a-time plain runs) run at their full shapes
+unless cut down by flags.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,6 +31,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+THERM_SWEEPS = 200     # thermalisation of the L = 4096 workload before any timing
+# Algorithmic bytes per spin update of one sweep with the fewest passes the
+# layout of the workloads allows: read labels + read spins + write spins +
+# write labels = 4 + 8 + 8 + 4 (32-bit labels), 8 + 8 + 8 + 8 (64-bit labels)
+SWEEP_BYTES = {32: 24.0, 64: 32.0}
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; a wave64 VALU
 # instruction occupies its SIMD for 4 cycles (= 39.3e12 lane-instructions/s)
 VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -112,17 +120,46 @@ def valu_from_counters(kernel: str):
     return rec.get("kernels", {}).get(kernel, {}).get("valu_insts")
 
 
-def cpu_baseline(L: int, beta: float, seed: int, nsweeps: int):
+def cpu_baseline(L: int, beta: float, seed: int, nsweeps: int, state):
+    """The oracle on this host's CPU, one thread, continuing the GPU's thermalised
+    lattice (state = (cos, sin, sweeps done)) for nsweeps sweeps."""
+    import numpy as np
+
     import oracle
 
-    lat = oracle.Lattice(L=L, beta=beta, seed=seed, storage32=True)
+    c, s, t = state
+    lat = oracle.Lattice(L=L, beta=beta, seed=seed, storage32=True, t=int(t), c=c.astype(np.float64),
+                         s=s.astype(np.float64))
     t0 = time.perf_counter()
     lat.run(nsweeps)
     dt = time.perf_counter() - t0
     return {"value": nsweeps * L * L / dt, "unit": "spin updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d sweeps of the L=%d, beta=%g lattice from the oracle's own hot start, "
-                      "1 thread (FP64, BFS labelling), %.1f s" % (nsweeps, L, beta, dt),
+            "sample": "%d sweeps (sweeps %d..%d) of the L=%d, beta=%g lattice continued from the GPU's "
+                      "thermalised state, 1 thread (FP64, BFS labelling), %.1f s" % (nsweeps, t, t + nsweeps - 1,
+                                                                                     L, beta, dt),
             "host_cpus": os.cpu_count()}
+
+
+def copy_bandwidth(mib: int = 1024) -> float:
+    """GB/s of a plain device-to-device copy of mib MiB (read + write bytes
+    over the copy's time, HIP events), the achievable HBM figure of this box."""
+    import torch
+
+    src = torch.ones(mib * 2 ** 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * mib * 2 ** 20 / (ms * 1e-3) / 1e9
 
 
 def cpu_batched(specs, nsweeps: int):
@@ -246,51 +283,71 @@ def bench_batched(sweeps: int, nrep: int = 512):
             "unit": "spin updates/s", "speedup": dt_p / dt_b}
 
 
-def bench_serving(n_requests: int, sweeps_lo: int, sweeps_hi: int):
+def bench_serving(n_requests: int, sweeps_lo: int, sweeps_hi: int, sequential: bool = True):
     """Poisson (20/s) stream of PCC run requests, L = 256..8192, admitted by a
-    200 GB HBM budget and 64 slots, served by continuous batching."""
+    200 GB HBM budget and 64 slots, served by continuous batching; then the same
+    trace one request at a time on plain handles (same PCC rule, same random
+    streams, so every request ends with the same beta bit for bit)."""
     import xyworkloads as wl
-    from paper_1210_6116_amd.serve import serve
+    from paper_1210_6116_amd.serve import serve, serve_sequential
 
     trace = wl.serving_trace(n_requests=n_requests, sweeps_lo=sweeps_lo, sweeps_hi=sweeps_hi)
     last = [0.0]
 
-    def progress(done, total, t):
-        if t - last[0] >= 20.0 or done == total:
-            last[0] = t
-            print("bench: serving %d/%d requests done at %.0f s" % (done, total, t), file=sys.stderr, flush=True)
+    def progress_for(what):
+        def progress(done, total, t):
+            if t - last[0] >= 20.0 or done == total:
+                last[0] = t
+                print("bench: %s %d/%d requests done at %.0f s" % (what, done, total, t), file=sys.stderr,
+                      flush=True)
+        return progress
 
-    res = serve(trace, budget_bytes=200 * 10 ** 9, max_slots=64, round_sweeps=16, progress=progress)
+    res = serve(trace, budget_bytes=200 * 10 ** 9, max_slots=64, round_sweeps=16, progress=progress_for("served"))
     s = res["summary"]
     offered = s["offered_updates"] / (max(r["arrival"] for r in trace) + 1e-9)
-    return {"workload": "%d requests, Poisson rate 20/s, L = 2^(8..13), %d-%d sweeps each (the full trace has "
-                        "200 requests of 1000-10000 sweeps), PCC window 1, 200 GB budget, 64 slots, FIFO admission"
-                        % (n_requests, sweeps_lo, sweeps_hi),
-            "served_value": s["served_updates_per_s"], "unit": "spin updates/s",
-            "ttc_p50_s": s["ttc_p50_s"], "ttc_p99_s": s["ttc_p99_s"], "makespan_s": s["makespan_s"],
-            "mean_running": s["mean_running"], "offered_updates_per_s": offered}
+    out = {"workload": "%d requests, Poisson rate 20/s, L = 2^(8..13), %d-%d sweeps each, PCC window 1 (dbeta 0.004 "
+                       "halved every 250 steps, floor 0.0005), 200 GB budget, 64 slots, FIFO admission"
+                       % (n_requests, sweeps_lo, sweeps_hi),
+           "served_value": s["served_updates_per_s"], "unit": "spin updates/s",
+           "ttc_p50_s": s["ttc_p50_s"], "ttc_p99_s": s["ttc_p99_s"], "makespan_s": s["makespan_s"],
+           "mean_running": s["mean_running"], "offered_updates_per_s": offered}
+    if sequential:
+        last[0] = 0.0
+        seq = serve_sequential(trace, progress=progress_for("sequential plain"))
+        q = seq["summary"]
+        same = all(a["beta"] == b["beta"] for a, b in zip(res["requests"], seq["requests"]))
+        out["sequential_plain"] = {"value": q["served_updates_per_s"], "ttc_p50_s": q["ttc_p50_s"],
+                                   "ttc_p99_s": q["ttc_p99_s"], "makespan_s": q["makespan_s"],
+                                   "what": "the same trace, one request at a time in arrival order, each on its own "
+                                           "plain handle"}
+        out["served_over_sequential"] = s["served_updates_per_s"] / q["served_updates_per_s"]
+        out["final_beta_identical"] = same
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10,
+                    help="untimed sweeps after the %d thermalisation sweeps" % THERM_SWEEPS)
     ap.add_argument("--L", type=int, default=4096)
     ap.add_argument("--beta", type=float, default=1.12)
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--cpu-sweeps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
     ap.add_argument("--no-instrument", action="store_true", help="skip the instrumented pass")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the L=65536 PCC, batched and serving legs")
     ap.add_argument("--extras", default="l65536,batched,serving",
                     help="comma-separated subset of the extra workloads to run")
-    ap.add_argument("--l65536-sweeps", type=int, default=100)
-    ap.add_argument("--batched-sweeps", type=int, default=100)
-    ap.add_argument("--serve-requests", type=int, default=40)
-    ap.add_argument("--serve-sweeps-lo", type=int, default=200)
-    ap.add_argument("--serve-sweeps-hi", type=int, default=2000)
+    ap.add_argument("--l65536-sweeps", type=int, default=2000)
+    ap.add_argument("--batched-sweeps", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-sweeps-lo", type=int, default=1000)
+    ap.add_argument("--serve-sweeps-hi", type=int, default=10000)
+    ap.add_argument("--no-serve-sequential", action="store_true",
+                    help="skip the one-request-at-a-time plain leg of the serving trace")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -304,6 +361,7 @@ def main():
     import paper_1210_6116_amd as xy
     import xyworkloads as wl
 
+    t_start = time.perf_counter()
     if args.copy_calib_mb:
         src = torch.ones(args.copy_calib_mb * 2 ** 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -315,13 +373,17 @@ def main():
     L, beta = args.L, args.beta
     N = L * L
     seed = wl.SEED_L4096
-    print("bench: L=%d beta=%g warmup=%d steps=%d" % (L, beta, args.warmup, args.steps), file=sys.stderr, flush=True)
+    print("bench: L=%d beta=%g thermalisation=%d warmup=%d steps=%d" % (L, beta, THERM_SWEEPS, args.warmup,
+                                                                      args.steps), file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
     lat = xy.Lattices(dict(L=L, beta=beta, seed=seed, tile_rows=args.tile_rows), stream=stream)
     label_bits = 64 if N >= 2 ** 32 else 32
     rows = args.tile_rows or 32
 
-    lat.sweep(args.warmup)
+    lat.sweep(THERM_SWEEPS + args.warmup)
+    torch.cuda.synchronize()
+    # the thermalised lattice the CPU oracle continues from
+    therm_state = (*lat.get_state(), lat.sweep_count()[0]) if not args.no_cpu else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat.sweep(args.steps)
@@ -330,6 +392,7 @@ def main():
     value = args.steps * N / dt
     print("bench: timed %d sweeps in %.3f s" % (args.steps, dt), file=sys.stderr, flush=True)
 
+    bps = SWEEP_BYTES[label_bits]
     roofline = None
     valu_issue = None
     latency = {}
@@ -348,17 +411,26 @@ def main():
             if launches[k] and name != "sweep":
                 avg = ms[k] / launches[k]
                 ab = alg_bytes_per_site(name, rows) * N
-                kernels[name] = {"launches": int(launches[k]), "avg_ms": avg, "alg_bytes": ab,
-                                 "alg_GBps": (ab / (avg * 1e-3) / 1e9) if ab else None}
+                kernels[name] = {"launches": int(launches[k]), "avg_ms": avg, "design_bytes": ab,
+                                 "design_GBps": (ab / (avg * 1e-3) / 1e9) if ab else None}
         dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-        if kernels[dom]["alg_bytes"] == 0:
-            dom = max((k for k in kernels if kernels[k]["alg_bytes"]),
-                      key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
         kd = kernels[dom]
-        achieved = kd["alg_GBps"]
+        # the dominant kernel completes one sweep of every site per launch (the
+        # flip of one sweep and the links and labels of the next): its
+        # algorithmic bytes are the sweep's 24 B (32-bit labels) per site
+        alg = bps * N if dom == "fused" else kd["design_bytes"]
+        achieved = alg / (kd["avg_ms"] * 1e-3) / 1e9
+        copy_gbs = copy_bandwidth()
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(dom, N),
-                    "alg_bytes_per_launch": kd["alg_bytes"], "avg_launch_ms": kd["avg_ms"]}
+                    "alg_bytes_per_site": bps if dom == "fused" else alg / N, "alg_bytes_per_launch": alg,
+                    "avg_launch_ms": kd["avg_ms"], "launches": kd["launches"],
+                    # the kernel's own byte model (16-bit tile-local labels, edge records)
+                    "design_bytes_per_site": kd["design_bytes"] / N,
+                    "design_frac": kd["design_GBps"] / HBM_PEAK_GBS if kd["design_GBps"] else None,
+                    # the whole sweep (every kernel and launch gap) against the same roofline
+                    "sweep_achieved": value * bps / 1e9, "sweep_frac": value * bps / 1e9 / HBM_PEAK_GBS,
+                    "copy_GBps": copy_gbs, "copy_frac": copy_gbs / HBM_PEAK_GBS}
         vi = valu_from_counters(dom)
         if vi:
             # the same kernel against its instruction-issue ceiling
@@ -367,6 +439,8 @@ def main():
                           "unit": "T VALU lane-instructions/s", "frac": rate / VALU_PEAK_TLANE,
                           "valu_insts_per_launch": vi}
     lat.close()
+    del lat
+    torch.cuda.empty_cache()
 
     line = {
         "metric": "spin updates/sec (SW sweeps x L^2 / s)",
@@ -386,10 +460,11 @@ def main():
         "dtype": "f32 state, f64 reflection and sums",
         "data": "synthetic (seeded Philox hot start)",
         "config": {"workload": "plain SW sweep, 2D XY periodic L=%d, beta=%g, uint%d canonical labels "
-                               "(16-bit tile-local labels in the sweep), %d thermalisation + %d timed "
-                               "sweeps" % (L, beta, label_bits,
-                                                                         args.warmup, args.steps),
-                   "L": L, "beta": beta, "seed": seed, "parallelism": "single GPU"},
+                               "(16-bit tile-local labels in the sweep), hot start, %d thermalisation + %d "
+                               "warm-up sweeps untimed, %d timed sweeps" % (L, beta, label_bits, THERM_SWEEPS,
+                                                                            args.warmup, args.steps),
+                   "L": L, "beta": beta, "seed": seed, "thermalisation": THERM_SWEEPS,
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "valu_issue": valu_issue,
         "latency": latency,
@@ -401,22 +476,24 @@ def main():
         for key, name, fn in (("l65536", "L65536_pcc", lambda: bench_l65536(args.l65536_sweeps)),
                               ("batched", "batched_vs_plain", lambda: bench_batched(args.batched_sweeps)),
                               ("serving", "serving", lambda: bench_serving(args.serve_requests, args.serve_sweeps_lo,
-                                                                           args.serve_sweeps_hi))):
+                                                                           args.serve_sweeps_hi,
+                                                                           not args.no_serve_sequential))):
             if key not in chosen:
                 continue
-            print("bench: %s" % name, file=sys.stderr, flush=True)
+            print("bench: %s (at %.0f s)" % (name, time.perf_counter() - t_start), file=sys.stderr, flush=True)
             try:
                 extras[name] = fn()
             except Exception as exc:  # reported, not hidden: the headline line still prints
                 extras[name] = {"error": "%s: %s" % (type(exc).__name__, exc)}
-            print("bench: %s done" % name, file=sys.stderr, flush=True)
+            print("bench: %s done (at %.0f s)" % (name, time.perf_counter() - t_start), file=sys.stderr, flush=True)
         line["extras"] = extras
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)
+        line["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps, therm_state)
         bat = line.get("extras", {}).get("batched_vs_plain")
         if bat is not None and "error" not in bat:
             bat["cpu_baseline"] = cpu_batched(wl.batched_replicas(512), 1)
+    line["bench_wall_s"] = time.perf_counter() - t_start
     print(json.dumps(line), flush=True)
 
 

@@ -46,7 +46,7 @@ enum {
     XY_ENOMEM = -2,  /* device or host allocation failed, or the arena is too small */
     XY_EDEVICE = -3, /* a HIP call failed; the handle is poisoned */
     XY_ESTATE = -4,  /* the handle is poisoned or in the wrong state for the call */
-    XY_EBUDGET = -5  /* reserved for admission by memory budget (serving) */
+    XY_EBUDGET = -5  /* serving: no free slot or not enough free budget right now (xy_group_add) */
 };
 
 enum { XY_START_HOT = 0 /* independent uniform angles */, XY_START_COLD = 1 /* theta = 0 */ };
@@ -226,7 +226,9 @@ int xy_group_create(size_t budget_bytes, int32_t max_slots, const xy_pcc *c, voi
                     xy_group **out);
 /* Admits a request of nsweeps >= 1 sweeps (label_bits must resolve to 32).
  * *slot receives its slot id.  XY_EBUDGET if no slot or not enough free
- * memory right now (nothing changes); XY_EINVAL for bad parameters. */
+ * memory right now (nothing changes; the request may fit later); XY_EINVAL
+ * for bad parameters, and for a request larger than the whole budget (it can
+ * never be admitted). */
 int xy_group_add(xy_group *g, const xy_params *p, int64_t nsweeps, int32_t *slot);
 /* Bytes a request of these parameters occupies in the group's arena. */
 int xy_group_bytes(const xy_params *p, size_t *bytes);
@@ -239,6 +241,10 @@ int xy_group_poll(xy_group *g, int32_t *slots, int32_t cap, int32_t *n);
 /* Result of a finished (or running) request: observables after its latest
  * sweep, its current beta, and the mean of beta over its PCC steps. */
 int xy_group_result(xy_group *g, int32_t slot, xy_obs *last, double *beta, double *beta_mean);
+/* Spins of a request (finished, or running after at least one round) as
+ * host arrays of N = L*L floats each (synchronizes).  XY_ESTATE before the
+ * request's first round. */
+int xy_group_get_state(xy_group *g, int32_t slot, float *cos_out, float *sin_out);
 /* Frees a finished request's slot and memory. */
 int xy_group_release(xy_group *g, int32_t slot);
 /* Bytes in use and running requests. */

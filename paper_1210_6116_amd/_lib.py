@@ -92,6 +92,7 @@ _SIGS = {
     "xy_group_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int32)]),
     "xy_group_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, _P(ctypes.c_double),
                                        _P(ctypes.c_double)]),
+    "xy_group_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "xy_group_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "xy_group_info": (ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_size_t), _P(ctypes.c_int32)]),
     "xy_group_free": (ctypes.c_int, [ctypes.c_void_p]),
@@ -266,6 +267,10 @@ def xy_group_result(g, slot: int):
     mean = ctypes.c_double(0.0)
     _check(load().xy_group_result(g, slot, _ptr(last), ctypes.byref(beta), ctypes.byref(mean)))
     return last[0], beta.value, mean.value
+
+
+def xy_group_get_state(g, slot: int, c: np.ndarray, s: np.ndarray):
+    _check(load().xy_group_get_state(g, slot, _ptr(c), _ptr(s)))
 
 
 def xy_group_release(g, slot: int):

@@ -435,21 +435,33 @@ int xy_alloc(const xy_params *p, int32_t n, void *hip_stream, void *arena, size_
         std::memset(&s, 0, sizeof s);
         s.beta = p[k].beta;
     }
-    HIPCHECK(h, hipMemcpy(h->d_reps, h->reps.data(), n * sizeof(xy::RepDesc), hipMemcpyHostToDevice));
-    HIPCHECK(h, hipMemcpy(h->d_state, states.data(), n * sizeof(xy::RepState), hipMemcpyHostToDevice));
-    if (n > 1) {
-        HIPCHECK(h, hipMemcpy(h->d_tile_rep, tile_rep.data(), tile_rep.size() * sizeof(uint32_t),
-                              hipMemcpyHostToDevice));
-        HIPCHECK(h, hipMemcpy(h->d_fin_rep, fin_rep.data(), fin_rep.size() * sizeof(uint32_t),
-                              hipMemcpyHostToDevice));
+    // a HIP failure from here on releases the handle (its arena and stream)
+    // before returning: the caller receives no handle to free
+    auto init = [&]() -> int {
+        HIPCHECK(h, hipMemcpy(h->d_reps, h->reps.data(), n * sizeof(xy::RepDesc), hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy(h->d_state, states.data(), n * sizeof(xy::RepState), hipMemcpyHostToDevice));
+        if (n > 1) {
+            HIPCHECK(h, hipMemcpy(h->d_tile_rep, tile_rep.data(), tile_rep.size() * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice));
+            HIPCHECK(h, hipMemcpy(h->d_fin_rep, fin_rep.data(), fin_rep.size() * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice));
+        }
+        for (int32_t k = 0; k < n; ++k) {
+            HIPCHECK(h, xy::launch_init_spins(h->d_reps, k, P.res[k].N, p[k].start, h->stream));
+            HIPCHECK(h, xy::launch_init_fourier(h->d_reps, k, P.res[k].L, h->stream));
+            HIPCHECK(h, xy::launch_edge_refresh(h->d_reps, k, P.res[k].ntiles, h->stream));
+        }
+        HIPCHECK(h, xy::launch_init_dir(h->d_reps, n, h->stream));
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        return XY_OK;
+    };
+    rc = init();
+    if (rc) {
+        const std::string msg = g_err;
+        xy_free(h);
+        g_err = msg;
+        return rc;
     }
-    for (int32_t k = 0; k < n; ++k) {
-        HIPCHECK(h, xy::launch_init_spins(h->d_reps, k, P.res[k].N, p[k].start, h->stream));
-        HIPCHECK(h, xy::launch_init_fourier(h->d_reps, k, P.res[k].L, h->stream));
-        HIPCHECK(h, xy::launch_edge_refresh(h->d_reps, k, P.res[k].ntiles, h->stream));
-    }
-    HIPCHECK(h, xy::launch_init_dir(h->d_reps, n, h->stream));
-    HIPCHECK(h, hipStreamSynchronize(h->stream));
     *out = h;
     return XY_OK;
 }
@@ -633,7 +645,14 @@ int xy_get_labels(xy_handle *h, int32_t rep, int64_t *out)
     if (!out) return fail(XY_EINVAL, "output pointer is NULL");
     const xy::RepDesc &d = h->reps[rep];
     void *tmp = nullptr;
-    HIPCHECK(h, hipMalloc(&tmp, d.N * sizeof(int64_t)));
+    const hipError_t ea = hipMalloc(&tmp, d.N * sizeof(int64_t));
+    if (ea != hipSuccess) {
+        // only the temporary buffer is missing: the handle stays usable, and
+        // the allocation error must not be reported by the next launch
+        (void)hipGetLastError();
+        return fail(XY_ENOMEM, "hipMalloc of %lld label bytes failed: %s", (long long)(d.N * sizeof(int64_t)),
+                    hipGetErrorString(ea));
+    }
     rc = xy_flatten_labels(h, rep, tmp, 64);
     if (rc == XY_OK) {
         const hipError_t e = hipMemcpy(out, tmp, d.N * sizeof(int64_t), hipMemcpyDeviceToHost);
@@ -741,7 +760,10 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     const size_t total = align_up(off_cross + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
     char *mem = nullptr;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&mem), total);
-    if (e != hipSuccess) return fail(XY_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // not left for the next launch to report
+        return fail(XY_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    }
     xy::RepDesc d;
     std::memset(&d, 0, sizeof d);
     d.lab = reinterpret_cast<uint16_t *>(mem + off_lab);

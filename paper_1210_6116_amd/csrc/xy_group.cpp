@@ -250,6 +250,10 @@ int xy_group_add(xy_group *g, const xy_params *p, int64_t nsweeps, int32_t *slot
     Plan P;
     rc = plan_request(p, P);
     if (rc) return rc;
+    const size_t bytes = slot_bytes(P);
+    if (bytes > g->arena.size)
+        return fail(XY_EINVAL, "a request of %zu bytes can never fit the group's budget of %zu bytes", bytes,
+                    g->arena.size);
     int32_t s = -1;
     for (int32_t k = 0; k < (int32_t)g->slots.size(); ++k)
         if (!g->slots[k].used) {
@@ -257,7 +261,6 @@ int xy_group_add(xy_group *g, const xy_params *p, int64_t nsweeps, int32_t *slot
             break;
         }
     if (s < 0) return fail(XY_EBUDGET, "all %zu slots are in use", g->slots.size());
-    const size_t bytes = slot_bytes(P);
     size_t off = 0;
     if (!g->arena.take(bytes, &off)) return fail(XY_EBUDGET, "no %zu free bytes in the group's arena", bytes);
     Slot &sl = g->slots[s];
@@ -350,6 +353,22 @@ int xy_group_result(xy_group *g, int32_t slot, xy_obs *last, double *beta, doubl
     if (last) *last = st.last;
     if (beta) *beta = st.beta;
     if (beta_mean) *beta_mean = st.beta_n ? st.beta_sum / (double)st.beta_n : st.beta;
+    return XY_OK;
+}
+
+int xy_group_get_state(xy_group *g, int32_t slot, float *cos_out, float *sin_out)
+{
+    int rc = check_group(g);
+    if (rc) return rc;
+    if (slot < 0 || slot >= (int32_t)g->slots.size() || !g->slots[slot].used)
+        return fail(XY_EINVAL, "slot %d is not in use", slot);
+    if (!cos_out || !sin_out) return fail(XY_EINVAL, "output pointer is NULL");
+    const Slot &sl = g->slots[slot];
+    if (sl.needs_init) return fail(XY_ESTATE, "slot %d has not run a round yet", slot);
+    const size_t bytes = (size_t)sl.plan.res[0].N * sizeof(float);
+    GCHECK(g, hipStreamSynchronize(g->stream));
+    GCHECK(g, hipMemcpy(cos_out, g->mem + sl.off + sl.plan.lay[0].c, bytes, hipMemcpyDeviceToHost));
+    GCHECK(g, hipMemcpy(sin_out, g->mem + sl.off + sl.plan.lay[0].s, bytes, hipMemcpyDeviceToHost));
     return XY_OK;
 }
 

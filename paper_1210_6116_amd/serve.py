@@ -22,6 +22,12 @@ from ._lib import XY_START_HOT, xy_params, xy_pcc
 PCC_TARGET = 0.636508
 
 
+def request_bytes(L: int) -> int:
+    """Bytes one request of side L occupies in a group's budget (host-side arithmetic)."""
+    return _lib.xy_group_bytes(xy_params(L=L, beta=1.0, seed=0, replica=0, label_bits=0, start=XY_START_HOT,
+                                         tile_rows=0))
+
+
 class Group:
     """A native serving group on a torch stream."""
 
@@ -42,6 +48,13 @@ class Group:
 
     def result(self, slot: int):
         return _lib.xy_group_result(self.g, slot)
+
+    def get_state(self, slot: int, L: int):
+        """(cos, sin) float32 arrays of the request in `slot` (side L)."""
+        c = np.zeros(L * L, dtype=np.float32)
+        s = np.zeros(L * L, dtype=np.float32)
+        _lib.xy_group_get_state(self.g, slot, c, s)
+        return c, s
 
     def release(self, slot: int):
         _lib.xy_group_release(self.g, slot)
@@ -72,6 +85,13 @@ def serve(trace, budget_bytes: int = 200 * 10 ** 9, max_slots: int = 64, pcc: xy
     """
     if pcc is None:
         pcc = xy_pcc(window=1, dbeta0=0.004, dbeta_min=0.0005, halve_every=250, target=PCC_TARGET)
+    # a request larger than the whole budget could never be admitted, and FIFO
+    # admission would then wait for it for ever: refuse the trace up front
+    for k, r in enumerate(trace):
+        need = request_bytes(r["L"])
+        if need > budget_bytes:
+            raise ValueError("request %d (L=%d) needs %d bytes, more than the %d-byte budget"
+                             % (k, r["L"], need, budget_bytes))
     order = sorted(range(len(trace)), key=lambda k: trace[k]["arrival"])
     grp = Group(budget_bytes, max_slots, pcc)
     recs = {k: dict(trace[k]) for k in order}
@@ -118,3 +138,41 @@ def serve(trace, budget_bytes: int = 200 * 10 ** 9, max_slots: int = 64, pcc: xy
                              ttc_p50_s=float(np.percentile(ttc, 50)), ttc_p99_s=float(np.percentile(ttc, 99)),
                              mean_running=float(np.mean(running_samples)) if running_samples else 0.0,
                              offered_updates=updates))
+
+
+def serve_sequential(trace, pcc: xy_pcc | None = None, clock=time.perf_counter, sleep=time.sleep, progress=None):
+    """The same trace without batching: one request at a time in arrival order,
+    each on its own plain handle (one lattice, the same PCC rule), started when
+    it has arrived and the previous one has finished.  Same records and summary
+    as serve()."""
+    from . import Lattices
+
+    if pcc is None:
+        pcc = xy_pcc(window=1, dbeta0=0.004, dbeta_min=0.0005, halve_every=250, target=PCC_TARGET)
+    order = sorted(range(len(trace)), key=lambda k: trace[k]["arrival"])
+    recs = {k: dict(trace[k]) for k in order}
+    stream = torch.cuda.Stream()
+    t0 = clock()
+    for done, k in enumerate(order):
+        r = recs[k]
+        wait = r["arrival"] - (clock() - t0)
+        if wait > 0:
+            sleep(wait)
+        r["admitted"] = clock() - t0
+        lat = Lattices(dict(L=r["L"], beta=r["beta0"], seed=r["seed"], rep=k), stream=stream)
+        lat.pcc(r["sweeps"], pcc.window, pcc.dbeta0, dbeta_min=pcc.dbeta_min, halve_every=pcc.halve_every,
+                target=pcc.target)
+        beta = lat.beta()  # synchronizes the stream
+        last = lat.measure()[0]
+        lat.close()
+        done_t = clock() - t0
+        r.update(finished=done_t, ttc=done_t - r["arrival"], beta=beta, E=float(last["E"]), m2=float(last["m2"]))
+        if progress is not None:
+            progress(done + 1, len(order), done_t)
+    makespan = max(r["finished"] for r in recs.values()) - min(r["arrival"] for r in recs.values())
+    updates = sum(r["L"] * r["L"] * r["sweeps"] for r in recs.values())
+    ttc = np.array([r["ttc"] for r in recs.values()])
+    return dict(requests=[recs[k] for k in sorted(recs)],
+                summary=dict(n=len(recs), makespan_s=makespan, served_updates_per_s=updates / makespan,
+                             ttc_p50_s=float(np.percentile(ttc, 50)), ttc_p99_s=float(np.percentile(ttc, 99)),
+                             mean_running=1.0, offered_updates=updates))

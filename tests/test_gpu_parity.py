@@ -171,13 +171,15 @@ def test_batched_replicas_match_plain():
 
 def test_batched_512_replicas_sampled_against_oracle():
     # The batched workload at its full shape (512 replicas, L = 64 ... 2048, beta in
-    # [1.0, 1.2], 64-row tiles, sweeps replayed from a captured graph): replicas
-    # of every size up to 256 are checked against the oracle bit for bit
+    # [1.0, 1.2], 64-row tiles, sweeps replayed from a captured graph): two
+    # replicas of every size, L = 64 ... 2048, are checked against the oracle bit
+    # for bit (the L = 512 ... 2048 replicas carry most of the batch's work)
     xy = _gpu()
     specs = [dict(sp, tile_rows=64) for sp in wl.batched_replicas(512)]
     picks = []
-    for L in (64, 128, 256):
+    for L in (64, 128, 256, 512, 1024, 2048):
         picks += [k for k, sp in enumerate(specs) if sp["L"] == L][:2]
+    assert len(picks) == 12
     print("512-replica batch, sampled replicas %s" % picks, flush=True)
     batch = xy.Lattices(specs)
     nsw = 3
@@ -185,6 +187,7 @@ def test_batched_512_replicas_sampled_against_oracle():
     meas = batch.measure()
     for k in picks:
         sp = specs[k]
+        print("replica %d: L=%d beta=%.4f" % (k, sp["L"], sp["beta"]), flush=True)
         orc = oracle.Lattice(L=sp["L"], beta=sp["beta"], seed=sp["seed"], rep=sp["rep"], storage32=True)
         for _ in range(nsw):
             obs_o, _, _, _, lab_o = orc.sweep_detail()

@@ -93,6 +93,43 @@ def test_served_result_equals_plain_pcc_run():
     lat.close()
 
 
+def test_served_request_matches_oracle():
+    """One served request (L = 128, window-1 PCC with the halving schedule) in a
+    mix that changes around it, against the oracle's PCC run: the beta after
+    every sweep and the final spins bit for bit."""
+    import oracle
+    from paper_1210_6116_amd.serve import Group
+    L, seed, rep, sweeps = 128, 0x5E12BE, 3, 40
+    g = Group(2 * 10 ** 9, 8, _pcc())
+    # (round of admission, L, seed, replica, sweeps) of the other requests
+    others = [(0, 256, 11, 0, 17), (0, 64, 12, 1, 50), (5, 512, 13, 2, 9), (12, 128, 14, 4, 21), (30, 64, 15, 5, 40)]
+    target = g.add(L, seed, 1.0, sweeps, replica=rep)
+    assert target is not None
+    betas = []
+    slots = {}
+    for r in range(sweeps):
+        for (adm, Lo, so, ro, nso) in others:
+            if adm == r:
+                s = g.add(Lo, so, 1.0, nso, replica=ro)
+                assert s is not None
+                slots[s] = (Lo, so)
+        assert g.round(1) == 1
+        betas.append(g.result(target)[1])
+        for s in g.poll():
+            if s != target:
+                g.release(s)
+    c_g, s_g = g.get_state(target, L)
+    last, beta, _ = g.result(target)
+    g.release(target)
+    g.close()
+    orc = oracle.Lattice(L=L, beta=1.0, seed=seed, rep=rep, storage32=True)
+    btr, _ = orc.pcc(sweeps, 1, 0.004, dbeta_min=0.0005, halve_every=25)
+    assert np.array_equal(np.array(betas), btr), np.flatnonzero(np.array(betas) != btr)[:5]
+    assert beta == orc.beta
+    assert np.array_equal(c_g.astype(np.float64), orc.c) and np.array_equal(s_g.astype(np.float64), orc.s)
+    assert int(last["sweep"]) == sweeps
+
+
 def test_group_budget_and_release():
     from paper_1210_6116_amd import _lib
     from paper_1210_6116_amd.serve import Group
@@ -108,6 +145,10 @@ def test_group_budget_and_release():
     assert sorted(g.poll()) == sorted([s0, s1])
     g.release(s0)
     assert g.add(256, 3, 1.0, 5) is not None      # memory came back
+    # a request larger than the whole budget can never fit: an error, not a wait
+    with pytest.raises(_lib.XYError) as ei:
+        g.add(1024, 4, 1.0, 5)
+    assert ei.value.code == _lib.XY_EINVAL
     g.close()
 
 

@@ -14,9 +14,13 @@ oracle cannot hold it, so the sweep is checked
     at any size: a site's label is no larger than the site and labels itself;
     the two ends of every active link share a label; spins stay unit vectors;
     and the observables equal an FP64 recomputation of the sums from the state.
-Whether two distinct components were wrongly united is not decided at this
-size (that needs a labelling of the whole lattice); the small-size parity
-tests decide it exactly.
+  * for at least 50 seeded sites whose clusters hold at most 10^5 sites (sites
+    in the bottom rows among them, whose cluster keys are near 2^32, the top of
+    the 32-bit node and key range of the boundary forest): a breadth-first
+    search on the host over the device's link bits, fetched by windows around
+    the site, gives exactly the set of sites that carry the site's device label
+    (same size as the device count of that label, and its smallest site is the
+    label), so no other cluster was united with it and none of it is missing.
 """
 import numpy as np
 import pytest
@@ -24,6 +28,7 @@ import torch
 
 import oracle
 import xyworkloads as wl
+from clusters import host_cluster
 
 pytestmark = pytest.mark.gpu
 
@@ -155,6 +160,32 @@ def test_l65536_sampled_oracle_and_invariants():
         n_active += int(ax.sum()) + int(ay.sum())
         del root, rr, ax, ay, down_roots, idx
     assert 0 < n_active < 2 * N
+
+    # 3b. no over-merging: host BFS of sampled clusters of at most 1e5 sites
+    print("L=65536 over-merge check", flush=True)
+    rng2 = np.random.default_rng(0x0E6E)
+    cand = np.concatenate([rng2.integers(0, N, 120),
+                           (L - 1 - rng2.integers(0, 256, 80)) * L + rng2.integers(0, L, 80)])
+    checked = high = 0
+    for cs in cand:
+        cs = int(cs)
+        lbl = int(lab[cs])
+        cnt = int((lab == lbl).sum())
+        if cnt > 100000:
+            continue
+        members = host_cluster(bxw, byw, L, cs)
+        if members is None:
+            continue
+        assert members.size == cnt, (cs, lbl, members.size, cnt)
+        assert int(members.min()) == lbl, (cs, lbl, int(members.min()))
+        got = lab.index_select(0, torch.from_numpy(members).to(dev))
+        assert bool((got == lbl).all()), (cs, lbl)
+        checked += 1
+        high += cs >= (L - 256) * L
+        if checked >= 60 and high >= 20:
+            break
+    print("over-merge check: %d clusters (%d in the bottom rows)" % (checked, high), flush=True)
+    assert checked >= 50 and high >= 10
 
     # 4. unit spins and observables from an FP64 recomputation of the sums
     print("L=65536 observables", flush=True)
