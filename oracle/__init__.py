@@ -87,6 +87,9 @@ def _load():
         "orc_run": (i32, [i64, dp, dp, dbl, u64, u32, u64, i64, i32, dp, i64p]),
         "orc_pcc_run": (i32, [i64, dp, dp, dp, u64, u32, u64, i64, i64, dbl, dbl, i64, dbl, i64,
                               i32, dp, dp]),
+        "orc_wrap": (i32, [i64, u8p, u8p, P(ctypes.c_int)]),
+        "orc_pcc_perc_run": (i32, [i64, dp, dp, dp, u64, u32, u64, i64, i64, dbl, dbl, i64, dbl, i64,
+                                   i32, dp, dp, P(ctypes.c_int32)]),
         "metro_run": (dbl, [i64, dbl, dbl, u64, i64, i64, dp, dp]),
     }
     for name, (res, args) in sig.items():
@@ -189,6 +192,17 @@ def label(L, bx, by) -> np.ndarray:
     return out
 
 
+def wrap(L, bx, by) -> int:
+    """Wrapping of the clusters of a link set: bit 0 if some cluster winds
+    around the periodic lattice along x, bit 1 along y."""
+    bx = np.ascontiguousarray(bx, dtype=np.uint8)
+    by = np.ascontiguousarray(by, dtype=np.uint8)
+    w = ctypes.c_int(0)
+    if _load().orc_wrap(L, _ptr(bx, ctypes.c_uint8), _ptr(by, ctypes.c_uint8), ctypes.byref(w)) != 0:
+        raise MemoryError("oracle wrapping check ran out of memory")
+    return int(w.value)
+
+
 def flip(L, lab, c, s, r, seed, rep, t, storage32=True):
     """Reflect every cluster whose coin is set; returns new (cos, sin)."""
     c = np.array(c, dtype=np.float64)
@@ -277,6 +291,25 @@ class Lattice:
         self.beta = beta.value
         self.t += nsteps * window
         return btr, butr
+
+    def pcc_perc(self, nsteps: int, window: int, dbeta0: float, dbeta_min: float = 0.0,
+                 halve_every: int = 0, target: float = 0.5, k0: int = 0):
+        """nsteps steps of the percolation PCC rule; returns (beta after each
+        step, wrapping fraction of each window, wrap bits of every sweep)."""
+        beta = ctypes.c_double(self.beta)
+        btr = np.zeros(nsteps)
+        ptr_ = np.zeros(nsteps)
+        wtr = np.zeros(nsteps * window, dtype=np.int32)
+        rc = _load().orc_pcc_perc_run(self.L, _ptr(self.c, ctypes.c_double), _ptr(self.s, ctypes.c_double),
+                                      ctypes.byref(beta), self.seed, self.rep, self.t, nsteps, window,
+                                      dbeta0, dbeta_min, halve_every, target, k0, int(self.storage32),
+                                      _ptr(btr, ctypes.c_double), _ptr(ptr_, ctypes.c_double),
+                                      _ptr(wtr, ctypes.c_int32))
+        if rc != 0:
+            raise MemoryError("oracle PCC run ran out of memory")
+        self.beta = beta.value
+        self.t += nsteps * window
+        return btr, ptr_, wtr
 
 
 def metropolis(L: int, beta: float, nsweeps: int, ntherm: int = 1000, seed: int = 1,

@@ -406,3 +406,114 @@ int orc_pcc_run(int64_t L, double *c, double *s, double *beta, uint64_t seed, ui
     }
     return 0;
 }
+
+/* Wrapping of the clusters around the periodic lattice (the observation that */
+/* drives the original PCC rule: raise or lower the temperature according to */
+/* whether the clusters percolate).  On a torus a cluster percolates when it  */
+/* holds a closed path of active links that winds around the lattice: bit 0  */
+/* of *wrap is set if some cluster winds along x a nonzero number of times,  */
+/* bit 1 if some cluster winds along y.  Breadth-first search from every     */
+/* cluster's first site gives each site unwrapped coordinates (a step to the */
+/* right neighbour adds 1 to x, to the lower neighbour 1 to y, the reverse   */
+/* steps subtract 1); an active link that reaches an already visited site    */
+/* with other unwrapped coordinates closes a path whose winding is that      */
+/* difference divided by L.  Every link is examined from both ends, so every */
+/* fundamental cycle of the search trees is checked.  Returns -1 if memory   */
+/* ran out.                                                                   */
+int orc_wrap(int64_t L, const uint8_t *bx, const uint8_t *by, int *wrap)
+{
+    int64_t N = L * L;
+    int64_t *queue = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    int64_t *ux = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    int64_t *uy = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    uint8_t *seen = (uint8_t *)calloc((size_t)N, 1);
+    *wrap = 0;
+    if (!queue || !ux || !uy || !seen) {
+        free(queue); free(ux); free(uy); free(seen);
+        return -1;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        if (seen[i]) continue;
+        int64_t head = 0, tail = 0;
+        seen[i] = 1;
+        ux[i] = i % L;
+        uy[i] = i / L;
+        queue[tail++] = i;
+        while (head < tail) {
+            int64_t k = queue[head++];
+            int64_t x = k % L, y = k / L;
+            int64_t nb[4] = {right_of(k, L), down_of(k, L), y * L + (x + L - 1) % L,
+                             ((y + L - 1) % L) * L + x};
+            int on[4] = {bx[k], by[k], bx[nb[2]], by[nb[3]]};
+            int64_t dx[4] = {1, 0, -1, 0}, dy[4] = {0, 1, 0, -1};
+            for (int d = 0; d < 4; ++d) {
+                if (!on[d]) continue;
+                int64_t j = nb[d], ex = ux[k] + dx[d], ey = uy[k] + dy[d];
+                if (!seen[j]) {
+                    seen[j] = 1;
+                    ux[j] = ex;
+                    uy[j] = ey;
+                    queue[tail++] = j;
+                } else {
+                    if (ux[j] != ex) *wrap |= 1;
+                    if (uy[j] != ey) *wrap |= 2;
+                }
+            }
+        }
+    }
+    free(queue); free(ux); free(uy); free(seen);
+    return 0;
+}
+
+/* The original (percolation) PCC rule with the same windows and step sizes */
+/* as orc_pcc_run: each step runs `window` sweeps at fixed beta and observes */
+/* after every sweep whether some cluster of that sweep wraps around the     */
+/* lattice (along x or along y, orc_wrap); P is the fraction of the window's */
+/* sweeps in which one did.  If P is below target (e.g. 1/2: the clusters   */
+/* percolate less often than not) beta grows by dbeta (the temperature falls */
+/* and the links become more likely), otherwise it shrinks by dbeta.         */
+/* beta_trace, p_trace (nsteps) and wrap_trace (nsteps * window, the wrap    */
+/* bits of every sweep) may be NULL.                                          */
+int orc_pcc_perc_run(int64_t L, double *c, double *s, double *beta, uint64_t seed, uint32_t rep,
+                     uint64_t t0, int64_t nsteps, int64_t window, double dbeta0, double dbeta_min,
+                     int64_t halve_every, double target, int64_t k0, int storage32,
+                     double *beta_trace, double *p_trace, int32_t *wrap_trace)
+{
+    int64_t N = L * L;
+    uint8_t *bx = (uint8_t *)malloc((size_t)N), *by = (uint8_t *)malloc((size_t)N);
+    if (!bx || !by) {
+        free(bx); free(by);
+        return -1;
+    }
+    uint64_t t = t0;
+    int rc = 0;
+    for (int64_t k = 0; k < nsteps && rc == 0; ++k) {
+        int64_t hits = 0;
+        for (int64_t w = 0; w < window; ++w) {
+            double obs[8];
+            int64_t nt = 0;
+            int wr = 0;
+            if (orc_sweep(L, c, s, *beta, seed, rep, t, storage32, obs, &nt, bx, by, NULL) != 0 ||
+                orc_wrap(L, bx, by, &wr) != 0) {
+                rc = -1;
+                break;
+            }
+            if (wr) ++hits;
+            if (wrap_trace) wrap_trace[k * window + w] = wr;
+            ++t;
+        }
+        if (rc) break;
+        double p = (double)hits / (double)window;
+        double db = dbeta0;
+        if (halve_every > 0) {
+            int64_t halvings = (k0 + k) / halve_every;
+            db = ldexp(dbeta0, -(int)(halvings < 200 ? halvings : 200));
+        }
+        if (db < dbeta_min) db = dbeta_min;
+        *beta += (p < target) ? db : -db;
+        if (beta_trace) beta_trace[k] = *beta;
+        if (p_trace) p_trace[k] = p;
+    }
+    free(bx); free(by);
+    return rc;
+}

@@ -46,6 +46,14 @@ MUTANTS = [
     ("fourier_drops_sin_part", "xy_oracle.c", "obs[7] = (cre * cre + cim * cim + sre * sre + sim * sim) / (n * n);",
      "obs[7] = (cre * cre + sre * sre) / (n * n);",
      "test_oracle_physics.test_measure_matches_angle_formulas()"),
+    ("wrap_ignores_y", "xy_oracle.c", "if (uy[j] != ey) *wrap |= 2;", "if (uy[j] != ey) *wrap |= 0;",
+     "test_oracle_wrap.test_hand_built_sets()"),
+    ("wrap_left_step", "xy_oracle.c", "int64_t dx[4] = {1, 0, -1, 0}, dy[4] = {0, 1, 0, -1};",
+     "int64_t dx[4] = {1, 0, 1, 0}, dy[4] = {0, 1, 0, -1};", "test_oracle_wrap.test_l2_every_link_subset_against_the_cover()"),
+    ("wrap_x_as_y", "xy_oracle.c", "if (ux[j] != ex) *wrap |= 1;", "if (ux[j] != ex) *wrap |= 2;",
+     "test_oracle_wrap.test_symmetries()"),
+    ("perc_rule_direction", "xy_oracle.c", "*beta += (p < target) ? db : -db;", "*beta += (p > target) ? db : -db;",
+     "test_oracle_wrap.test_percolation_pcc_direction_of_steps()"),
     ("philox_key_bump", "xy_oracle.c", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE86u;",
      "test_oracle_philox.test_philox4x32_known_answers([0, 0, 0, 0], [0, 0], "
      "[0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8])"),
