@@ -444,10 +444,10 @@ int orc_wrap(int64_t L, const uint8_t *bx, const uint8_t *by, int *wrap)
             int64_t x = k % L, y = k / L;
             int64_t nb[4] = {right_of(k, L), down_of(k, L), y * L + (x + L - 1) % L,
                              ((y + L - 1) % L) * L + x};
-            int on[4] = {bx[k], by[k], bx[nb[2]], by[nb[3]]};
+            const int act[4] = {bx[k], by[k], bx[nb[2]], by[nb[3]]};
             int64_t dx[4] = {1, 0, -1, 0}, dy[4] = {0, 1, 0, -1};
             for (int d = 0; d < 4; ++d) {
-                if (!on[d]) continue;
+                if (!act[d]) continue;
                 int64_t j = nb[d], ex = ux[k] + dx[d], ey = uy[k] + dy[d];
                 if (!seen[j]) {
                     seen[j] = 1;
