@@ -190,6 +190,23 @@ int xy_get_sweep(xy_handle *h, int32_t rep, uint64_t *sweep, double r[2]);
 int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint32_t *d_bx,
                    const uint32_t *d_by, void *d_labels, void *hip_stream);
 
+/* xy_label_links for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same labelling, with its scratch (state and descriptor, tile-local
+ * labels, edge slots, boundary forest, edge-link masks) in a fixed 16 MiB
+ * device array of the library instead of a per-call allocation.  Each GPU the
+ * library runs on holds its own copy of that array until the process ends.
+ * Arguments as in xy_label_links; L*L plus the forest must fit the array
+ * (L <= 2048 for every tile height; larger lattices: XY_EINVAL, nothing
+ * enqueued).  Allocates nothing and does not synchronize: the work is only
+ * enqueued on hip_stream (NULL = the default stream), and d_labels is ready
+ * once that stream has reached it.  Every call on a GPU uses that GPU's one
+ * array, so calls that overlap on one GPU (different streams, or threads)
+ * race; calls on one stream are ordered.  The first call on each device takes
+ * the array's device address (hipGetSymbolAddress) with that device current. */
+int xy_label_links_noalloc(int64_t L, int32_t label_bits, int32_t tile_rows, const uint32_t *d_bx,
+                           const uint32_t *d_by, void *d_labels, void *hip_stream);
+
 /* Per-kernel timing with HIP events on the handle's stream: enable (1) or
  * disable (0) recording; read the accumulated milliseconds and launch counts
  * of each kernel class (XY_K_*) and reset them (synchronizes).  XY_K_SWEEP

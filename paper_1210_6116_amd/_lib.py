@@ -80,6 +80,8 @@ _SIGS = {
     "xy_get_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_uint64), ctypes.c_void_p]),
     "xy_label_links": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_label_links_noalloc": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "xy_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "xy_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_int64, _P(ctypes.c_int64)]),
@@ -204,6 +206,11 @@ def xy_get_sweep(h, rep: int):
 
 def xy_label_links(L: int, label_bits: int, tile_rows: int, d_bx: int, d_by: int, d_labels: int, stream=None):
     _check(load().xy_label_links(L, label_bits, tile_rows, d_bx, d_by, d_labels, stream))
+
+
+def xy_label_links_noalloc(L: int, label_bits: int, tile_rows: int, d_bx: int, d_by: int, d_labels: int,
+                           stream=None):
+    _check(load().xy_label_links_noalloc(L, label_bits, tile_rows, d_bx, d_by, d_labels, stream))
 
 
 def xy_timing(h, enable: bool):

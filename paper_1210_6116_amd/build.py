@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxy.so")
-SOURCES = ("xy_kernels.hip", "xy_api.cpp", "xy_group.cpp")
+SOURCES = ("xy_kernels.hip", "xy_api.cpp", "xy_group.cpp", "xy_noalloc.hip")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: the FP64 decision and reflection expressions are evaluated

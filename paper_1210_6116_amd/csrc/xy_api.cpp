@@ -199,6 +199,78 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
     d.idx = idx;
 }
 
+
+int plan_link_labels(int64_t L, int32_t label_bits, int32_t tile_rows, LinkLabelJob &J)
+{
+    xy_params p;
+    std::memset(&p, 0, sizeof p);
+    p.L = L;
+    p.label_bits = label_bits;
+    p.tile_rows = tile_rows;
+    if (label_bits != 32 && label_bits != 64) return fail(XY_EINVAL, "label_bits=%d is not 32 or 64", label_bits);
+    int rc = make_plan(&p, 1, J.plan);
+    if (rc) return rc;
+    const Resolved &r = J.plan.res[0];
+    const size_t nodes = (size_t)r.ntiles * r.nb;
+    static_assert(sizeof(xy::RepState) <= 512 && sizeof(xy::RepDesc) <= 512, "scratch header too small");
+    J.off_state = 0;
+    J.off_desc = 512;
+    J.off_lab = 1024;
+    J.off_bslot = align_up(J.off_lab + (size_t)r.N * sizeof(uint16_t));
+    J.off_node = align_up(J.off_bslot + nodes);
+    J.off_cross = align_up(J.off_node + nodes * sizeof(unsigned long long));
+    J.total = align_up(J.off_cross + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
+    return XY_OK;
+}
+
+void link_label_desc(const LinkLabelJob &J, char *mem, const uint32_t *d_bx, const uint32_t *d_by, xy::RepDesc &d)
+{
+    const Resolved &r = J.plan.res[0];
+    std::memset(&d, 0, sizeof d);
+    d.lab = reinterpret_cast<uint16_t *>(mem + J.off_lab);
+    d.bslot = reinterpret_cast<uint8_t *>(mem + J.off_bslot);
+    d.node = reinterpret_cast<unsigned long long *>(mem + J.off_node);
+    d.cross = reinterpret_cast<unsigned long long *>(mem + J.off_cross);
+    for (int q = 0; q < 2; ++q) {
+        d.bx[q] = const_cast<uint32_t *>(d_bx);
+        d.by[q] = const_cast<uint32_t *>(d_by);
+    }
+    d.st = reinterpret_cast<xy::RepState *>(mem + J.off_state);
+    d.L = r.L;
+    d.N = r.N;
+    d.ntiles = r.ntiles;
+    d.log2L = ilog2(r.L);
+    d.TW = r.TW;
+    d.TH = r.TH;
+    d.log2TW = ilog2(r.TW);
+    d.ntx = r.ntx;
+    d.nty = r.nty;
+    d.nb = r.nb;
+}
+
+hipError_t enqueue_link_labels(const LinkLabelJob &J, char *mem, void *d_labels, hipStream_t s)
+{
+    const Resolved &r = J.plan.res[0];
+    const xy::RepDesc *d_rep = reinterpret_cast<const xy::RepDesc *>(mem + J.off_desc);
+    xy::Launch lc;
+    lc.reps = d_rep;
+    lc.tile_rep = nullptr;
+    lc.nrep = 1;
+    lc.label_bits = J.plan.label_bits;
+    lc.max_th = r.TH;
+    lc.big_index = J.plan.big_index;
+    lc.uniform_tw = J.plan.uniform_tw;
+    lc.uniform_th = J.plan.uniform_th;
+    lc.gtile0 = 0;
+    lc.gtile_end = r.ntiles;
+    lc.fin_rep = nullptr;
+    lc.nfin = 0;  // no finalisation here
+    hipError_t e = xy::launch_tile(lc, xy::TILE_PLANES, s);
+    if (e == hipSuccess) e = xy::launch_merge(lc, false, false, s);
+    if (e == hipSuccess) e = xy::launch_flatten(d_rep, 0, r.N, J.plan.big_index, d_labels, J.plan.label_bits, s);
+    return e;
+}
+
 }  // namespace xyhost
 
 using namespace xyhost;
@@ -740,74 +812,24 @@ int xy_get_sweep(xy_handle *h, int32_t rep, uint64_t *sweep, double r[2])
 int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint32_t *d_bx, const uint32_t *d_by,
                    void *d_labels, void *hip_stream)
 {
-    xy_params p;
-    std::memset(&p, 0, sizeof p);
-    p.L = L;
-    p.label_bits = label_bits;
-    p.tile_rows = tile_rows;
     if (!d_bx || !d_by || !d_labels) return fail(XY_EINVAL, "device pointer is NULL");
-    if (label_bits != 32 && label_bits != 64) return fail(XY_EINVAL, "label_bits=%d is not 32 or 64", label_bits);
-    Plan P;
-    int rc = make_plan(&p, 1, P);
+    LinkLabelJob J;
+    int rc = plan_link_labels(L, label_bits, tile_rows, J);
     if (rc) return rc;
-    const Resolved &r = P.res[0];
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    // scratch: state + descriptor, then the tile-local labels and the forest
-    const size_t nodes = (size_t)r.ntiles * r.nb;
-    const size_t off_lab = 1024, off_bslot = align_up(off_lab + (size_t)r.N * sizeof(uint16_t));
-    const size_t off_node = align_up(off_bslot + nodes);
-    const size_t off_cross = align_up(off_node + nodes * sizeof(unsigned long long));
-    const size_t total = align_up(off_cross + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
     char *mem = nullptr;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&mem), total);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&mem), J.total);
     if (e != hipSuccess) {
         (void)hipGetLastError();  // not left for the next launch to report
         return fail(XY_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
     }
     xy::RepDesc d;
-    std::memset(&d, 0, sizeof d);
-    d.lab = reinterpret_cast<uint16_t *>(mem + off_lab);
-    d.bslot = reinterpret_cast<uint8_t *>(mem + off_bslot);
-    d.node = reinterpret_cast<unsigned long long *>(mem + off_node);
-    d.cross = reinterpret_cast<unsigned long long *>(mem + off_cross);
-    for (int q = 0; q < 2; ++q) {
-        d.bx[q] = const_cast<uint32_t *>(d_bx);
-        d.by[q] = const_cast<uint32_t *>(d_by);
-    }
-    d.L = r.L;
-    d.N = r.N;
-    d.ntiles = r.ntiles;
-    d.log2L = ilog2(r.L);
-    d.TW = r.TW;
-    d.TH = r.TH;
-    d.log2TW = ilog2(r.TW);
-    d.ntx = r.ntx;
-    d.nty = r.nty;
-    d.nb = r.nb;
+    link_label_desc(J, mem, d_bx, d_by, d);
     xy::RepState st;
     std::memset(&st, 0, sizeof st);
-    xy::RepState *d_st = reinterpret_cast<xy::RepState *>(mem);
-    xy::RepDesc *d_rep = reinterpret_cast<xy::RepDesc *>(mem + 512);
-    static_assert(sizeof(xy::RepState) <= 512 && sizeof(xy::RepDesc) <= 512, "scratch header too small");
-    d.st = d_st;
-    e = hipMemcpy(d_st, &st, sizeof st, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_rep, &d, sizeof d, hipMemcpyHostToDevice);
-    xy::Launch lc;
-    lc.reps = d_rep;
-    lc.tile_rep = nullptr;
-    lc.nrep = 1;
-    lc.label_bits = label_bits;
-    lc.max_th = r.TH;
-    lc.big_index = P.big_index;
-    lc.uniform_tw = P.uniform_tw;
-    lc.uniform_th = P.uniform_th;
-    lc.gtile0 = 0;
-    lc.gtile_end = r.ntiles;
-    lc.fin_rep = nullptr;
-    lc.nfin = 0;  // no finalisation here
-    if (e == hipSuccess) e = xy::launch_tile(lc, xy::TILE_PLANES, s);
-    if (e == hipSuccess) e = xy::launch_merge(lc, false, false, s);
-    if (e == hipSuccess) e = xy::launch_flatten(d_rep, 0, r.N, P.big_index, d_labels, label_bits, s);
+    e = hipMemcpy(mem + J.off_state, &st, sizeof st, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mem + J.off_desc, &d, sizeof d, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = enqueue_link_labels(J, mem, d_labels, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(mem);
     if (e != hipSuccess) return fail(XY_EDEVICE, "labelling failed: %s", hipGetErrorString(e));

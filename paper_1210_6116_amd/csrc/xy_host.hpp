@@ -48,6 +48,20 @@ int make_plan(const xy_params *p, int32_t n, Plan &P);
 // Descriptor of replica k of plan P whose buffers start at base (layout P.lay[k]).
 void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *base, xy::RepState *st, int64_t tile_base,
                int64_t fin_base, int32_t idx, xy::RepDesc &d);
+// Standalone labelling of a given link set (xy_label_links and its variant
+// without allocation): the plan of one replica and the byte layout of its
+// scratch (state and descriptor, tile-local labels, edge slots, forest,
+// edge-link masks).
+struct LinkLabelJob {
+    Plan plan;
+    size_t off_state = 0, off_desc = 0, off_lab = 0, off_bslot = 0, off_node = 0, off_cross = 0, total = 0;
+};
+int plan_link_labels(int64_t L, int32_t label_bits, int32_t tile_rows, LinkLabelJob &J);
+// Descriptor of the labelling whose scratch starts at the device address mem.
+void link_label_desc(const LinkLabelJob &J, char *mem, const uint32_t *d_bx, const uint32_t *d_by, xy::RepDesc &d);
+// Tile labelling from the bit planes, merge across tiles and canonical labels
+// into d_labels; the scratch must already hold the state and the descriptor.
+hipError_t enqueue_link_labels(const LinkLabelJob &J, char *mem, void *d_labels, hipStream_t s);
 // Launch state carried from one sweep to the next inside a sequence.
 struct Pipe {
     bool ready = false;        // the links of the next sweep are activated and labelled
