@@ -15,7 +15,9 @@ per-sweep p50 / p99 latency.  The CPU oracle is timed on 20 sweeps of the
 GPU's thermalised lattice on this host (cpu_baseline).  The other workloads
 (L = 65536 PCC run, 512-replica batch against plain handles, the serving
 trace against one-request-at-a-time plain runs) run at their full shapes
-unless cut down by flags.  Prints one JSON line.
+unless cut down by flags; a leg that would run past --time-budget seconds of
+bench time is skipped (and says so), and the sequential serving leg starts no
+request after it.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -283,7 +285,7 @@ def bench_batched(sweeps: int, nrep: int = 512):
             "unit": "spin updates/s", "speedup": dt_p / dt_b}
 
 
-def bench_serving(n_requests: int, sweeps_lo: int, sweeps_hi: int, sequential: bool = True):
+def bench_serving(n_requests: int, sweeps_lo: int, sweeps_hi: int, sequential: bool = True, deadline=None):
     """Poisson (20/s) stream of PCC run requests, L = 256..8192, admitted by a
     200 GB HBM budget and 64 slots, served by continuous batching; then the same
     trace one request at a time on plain handles (same PCC rule, same random
@@ -313,13 +315,17 @@ def bench_serving(n_requests: int, sweeps_lo: int, sweeps_hi: int, sequential: b
            "mean_running": s["mean_running"], "offered_updates_per_s": offered}
     if sequential:
         last[0] = 0.0
-        seq = serve_sequential(trace, progress=progress_for("sequential plain"))
+        seq = serve_sequential(trace, progress=progress_for("sequential plain"), deadline=deadline)
         q = seq["summary"]
-        same = all(a["beta"] == b["beta"] for a, b in zip(res["requests"], seq["requests"]))
+        served_by_id = {(r["seed"], r["arrival"]): r for r in res["requests"]}
+        same = all(served_by_id[(b["seed"], b["arrival"])]["beta"] == b["beta"] for b in seq["requests"])
         out["sequential_plain"] = {"value": q["served_updates_per_s"], "ttc_p50_s": q["ttc_p50_s"],
                                    "ttc_p99_s": q["ttc_p99_s"], "makespan_s": q["makespan_s"],
+                                   "requests": q["n"], "complete": q["complete"],
                                    "what": "the same trace, one request at a time in arrival order, each on its own "
-                                           "plain handle"}
+                                           "plain handle" + ("" if q["complete"] else
+                                                             "; stopped at the bench's time budget after the first "
+                                                             "%d requests (rate over those)" % q["n"])}
         out["served_over_sequential"] = s["served_updates_per_s"] / q["served_updates_per_s"]
         out["final_beta_identical"] = same
     return out
@@ -348,6 +354,9 @@ def main():
     ap.add_argument("--serve-sweeps-hi", type=int, default=10000)
     ap.add_argument("--no-serve-sequential", action="store_true",
                     help="skip the one-request-at-a-time plain leg of the serving trace")
+    ap.add_argument("--time-budget", type=float, default=520.0,
+                    help="seconds of bench wall time after which no further extra leg starts (the serving "
+                         "trace's sequential leg stops starting requests); the headline line always prints")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -380,10 +389,8 @@ def main():
     label_bits = 64 if N >= 2 ** 32 else 32
     rows = args.tile_rows or 32
 
-    lat.sweep(THERM_SWEEPS + args.warmup)
-    torch.cuda.synchronize()
-    # the thermalised lattice the CPU oracle continues from
-    therm_state = (*lat.get_state(), lat.sweep_count()[0]) if not args.no_cpu else None
+    lat.sweep(THERM_SWEEPS)
+    lat.sweep(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat.sweep(args.steps)
@@ -438,9 +445,16 @@ def main():
             valu_issue = {"bound": "alu", "kernel": dom, "achieved": rate, "peak": VALU_PEAK_TLANE,
                           "unit": "T VALU lane-instructions/s", "frac": rate / VALU_PEAK_TLANE,
                           "valu_insts_per_launch": vi}
+    # the thermalised lattice the CPU oracle continues from (taken after the
+    # timed sweeps, so that no host copy idles the GPU before them)
+    therm_state = (*lat.get_state(), lat.sweep_count()[0]) if not args.no_cpu else None
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(L, beta, seed, args.cpu_sweeps, therm_state)
 
     line = {
         "metric": "spin updates/sec (SW sweeps x L^2 / s)",
@@ -470,29 +484,41 @@ def main():
         "latency": latency,
         "kernels": kernels,
     }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     if not args.no_extras:
         extras = {}
         chosen = set(args.extras.split(","))
+        deadline = t_start + args.time_budget
+        # rough wall time of each leg at MI355X speed (seconds), to skip a leg
+        # that would run past the budget rather than be cut off by a caller
+        est = {"l65536": 8.0 + 0.04 * args.l65536_sweeps, "batched": 12.0 + 0.025 * args.batched_sweeps,
+               # the served pass: requests x mean L^2 (1.49e7 for L = 256..8192) x mean sweeps at ~1e11 updates/s
+               # (the sequential pass after it stops starting requests at the deadline)
+               "serving": 10.0 + args.serve_requests * 1.49e7 * (args.serve_sweeps_lo + args.serve_sweeps_hi) / 2.0
+               / 1.0e11}
         for key, name, fn in (("l65536", "L65536_pcc", lambda: bench_l65536(args.l65536_sweeps)),
                               ("batched", "batched_vs_plain", lambda: bench_batched(args.batched_sweeps)),
                               ("serving", "serving", lambda: bench_serving(args.serve_requests, args.serve_sweeps_lo,
                                                                            args.serve_sweeps_hi,
-                                                                           not args.no_serve_sequential))):
+                                                                           not args.no_serve_sequential,
+                                                                           deadline=deadline))):
             if key not in chosen:
                 continue
-            print("bench: %s (at %.0f s)" % (name, time.perf_counter() - t_start), file=sys.stderr, flush=True)
+            now = time.perf_counter()
+            if now + est[key] > deadline:
+                extras[name] = {"skipped": "time budget: %.0f s left of --time-budget %.0f, the leg takes about %.0f s"
+                                           % (deadline - now, args.time_budget, est[key])}
+                continue
+            print("bench: %s (at %.0f s)" % (name, now - t_start), file=sys.stderr, flush=True)
             try:
                 extras[name] = fn()
             except Exception as exc:  # reported, not hidden: the headline line still prints
                 extras[name] = {"error": "%s: %s" % (type(exc).__name__, exc)}
             print("bench: %s done (at %.0f s)" % (name, time.perf_counter() - t_start), file=sys.stderr, flush=True)
+            if key == "batched" and not args.no_cpu and "error" not in extras[name]:
+                extras[name]["cpu_baseline"] = cpu_batched(wl.batched_replicas(512), 1)
         line["extras"] = extras
-    if not args.no_cpu:
-        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps, therm_state)
-        bat = line.get("extras", {}).get("batched_vs_plain")
-        if bat is not None and "error" not in bat:
-            bat["cpu_baseline"] = cpu_batched(wl.batched_replicas(512), 1)
     line["bench_wall_s"] = time.perf_counter() - t_start
     print(json.dumps(line), flush=True)
 

@@ -81,16 +81,36 @@ typedef struct {
     double mk2;         /* |sum_r s(r) exp(i k x)|^2 / N^2 at k = 2 pi / L: chi(k) / N of the
                            second-moment correlation length (m2 is chi(0) / N) */
     uint64_t near_ties; /* bond decisions of the sweep with |u - p| < 1e-9 */
+    uint64_t wrap;      /* percolation-rule runs (XY_PCC_PERCOLATION): 4 | bit 0 if some cluster of the
+                           sweep winds around the periodic lattice along x (holds a closed path of active
+                           links with nonzero x winding number) | bit 1 the same along y; window means:
+                           4 | the union of the window's bits.  0 when the check did not run. */
+    double perc;        /* percolation-rule runs: 1 if some cluster winds (along x or y), else 0; window
+                           means: the fraction of the window's sweeps in which one did.  -1 when the
+                           check did not run. */
 } xy_obs;
 
-/* Generalized PCC controller (paper: the PCC paragraph and the simulation
- * paragraph: windows of 1000 MCS, dbeta = 0.0005, target 0.636508). */
+/* PCC controller (paper: the PCC paragraph and the simulation paragraph:
+ * windows of 1000 MCS, dbeta = 0.0005, target 0.636508).  Two rules:
+ *   XY_PCC_HELICITY   the generalized rule the paper uses: beta*Upsilon of the
+ *                     window (from the means of e_x and N s_x^2) below target
+ *                     -> beta += dbeta, otherwise beta -= dbeta;
+ *   XY_PCC_PERCOLATION  the original rule of the PCC paragraph (raise or lower
+ *                     the temperature according to whether the clusters
+ *                     percolate): after every sweep the library checks whether
+ *                     some cluster winds around the periodic lattice (along x
+ *                     or y; xy_obs.wrap); the fraction P of the window's sweeps
+ *                     in which one did below target (e.g. 0.5) -> beta +=
+ *                     dbeta, otherwise beta -= dbeta.  Needs L <= 4096. */
+enum { XY_PCC_HELICITY = 0, XY_PCC_PERCOLATION = 1 };
 typedef struct {
     int64_t window;      /* sweeps per PCC step, >= 1 */
     double dbeta0;       /* step of the first PCC step, > 0 */
     double dbeta_min;    /* floor of the halving schedule, >= 0 */
     int64_t halve_every; /* PCC steps between halvings of dbeta; 0 = never */
-    double target;       /* critical beta*Upsilon, e.g. 0.636508 */
+    double target;       /* critical beta*Upsilon, e.g. 0.636508; percolation rule: critical P, e.g. 0.5 */
+    int32_t rule;        /* XY_PCC_HELICITY or XY_PCC_PERCOLATION */
+    int32_t reserved;    /* 0 */
 } xy_pcc;
 
 /* Device bytes that xy_alloc needs for these n replicas (arena size). */
@@ -124,7 +144,10 @@ int xy_measure(xy_handle *h, xy_obs *out);
 /* Runs nsteps >= 1 PCC steps of c->window sweeps each, updating every
  * replica's beta on the device after each window.  window_mean: NULL, or host
  * memory for nsteps * n xy_obs receiving the window means (beta = the new
- * beta) as window_mean[k * n + rep] (synchronizes). */
+ * beta) as window_mean[k * n + rep] (synchronizes).  The first call with the
+ * percolation rule allocates the handle's wrapping-check buffers (four 64-bit
+ * words per tile-edge position, kept until xy_free); XY_EINVAL if a replica
+ * has L > 4096 for that rule. */
 int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_mean);
 
 /* Releases the handle and whatever the library allocated.  xy_free(NULL) is OK. */
@@ -221,7 +244,8 @@ enum {
     XY_K_FINALIZE = 4, /* observables, PCC step, counters */
     XY_K_COINS = 5,    /* coins of the clusters at tile edges */
     XY_K_SWEEP = 6,
-    XY_K_COUNT = 7
+    XY_K_WRAP = 7,     /* wrapping check of the percolation rule (forest copies, cut merges, check) */
+    XY_K_COUNT = 8
 };
 int xy_timing(xy_handle *h, int32_t enable);
 int xy_timing_read(xy_handle *h, double *ms, int64_t *launches, double *samples, int64_t cap,
@@ -238,7 +262,8 @@ int xy_timing_read(xy_handle *h, double *ms, int64_t *launches, double *samples,
 typedef struct xy_group xy_group;
 
 /* budget_bytes: device memory the group may use (one arena, allocated here);
- * max_slots >= 1; c: PCC rule of every request; hip_stream as in xy_alloc. */
+ * max_slots >= 1; c: PCC rule of every request (XY_PCC_HELICITY only);
+ * hip_stream as in xy_alloc. */
 int xy_group_create(size_t budget_bytes, int32_t max_slots, const xy_pcc *c, void *hip_stream,
                     xy_group **out);
 /* Admits a request of nsweeps >= 1 sweeps (label_bits must resolve to 32).

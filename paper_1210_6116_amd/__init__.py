@@ -18,10 +18,11 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (OBS_DTYPE, XY_START_COLD, XY_START_HOT, XYError, xy_obs, xy_params, xy_pcc)
+from ._lib import (OBS_DTYPE, XY_PCC_HELICITY, XY_PCC_PERCOLATION, XY_START_COLD, XY_START_HOT, XYError, xy_obs,
+                   xy_params, xy_pcc)
 
 __all__ = ["Lattices", "XYError", "OBS_DTYPE", "XY_START_HOT", "XY_START_COLD", "PCC_TARGET",
-           "unpack_bits", "xy_params", "xy_obs", "xy_pcc"]
+           "unpack_bits", "xy_params", "xy_obs", "xy_pcc", "XY_PCC_HELICITY", "XY_PCC_PERCOLATION"]
 
 PCC_TARGET = 0.636508  # critical beta*Upsilon with the periodic-boundary winding correction
 
@@ -77,9 +78,12 @@ class Lattices:
         return out
 
     def pcc(self, nsteps: int, window: int, dbeta0: float, dbeta_min: float = 0.0, halve_every: int = 0,
-            target: float = PCC_TARGET, means: bool = False):
-        """nsteps PCC steps of `window` sweeps; with means=True returns window means [nsteps, n]."""
-        c = xy_pcc(window=window, dbeta0=dbeta0, dbeta_min=dbeta_min, halve_every=halve_every, target=target)
+            target: float = PCC_TARGET, means: bool = False, rule: int = XY_PCC_HELICITY):
+        """nsteps PCC steps of `window` sweeps; with means=True returns window means [nsteps, n].
+        rule: XY_PCC_HELICITY (the paper's rule, target 0.636508) or XY_PCC_PERCOLATION
+        (the original rule on whether the clusters wind around the lattice, target e.g. 0.5)."""
+        c = xy_pcc(window=window, dbeta0=dbeta0, dbeta_min=dbeta_min, halve_every=halve_every, target=target,
+                   rule=rule)
         out = np.zeros((nsteps, self.n), dtype=OBS_DTYPE) if means else None
         _lib.xy_pcc_step(self.h, c, nsteps, out)
         return out

@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxy.so")
 
 XY_OK, XY_EINVAL, XY_ENOMEM, XY_EDEVICE, XY_ESTATE, XY_EBUDGET = 0, -1, -2, -3, -4, -5
 XY_START_HOT, XY_START_COLD = 0, 1
-XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_FINALIZE, XY_K_COINS, XY_K_SWEEP, XY_K_COUNT = range(8)
-KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize", "coins", "sweep")
+XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_FINALIZE, XY_K_COINS, XY_K_SWEEP, XY_K_WRAP, XY_K_COUNT = range(9)
+KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize", "coins", "sweep", "wrap")
+XY_PCC_HELICITY, XY_PCC_PERCOLATION = 0, 1
 
 
 class XYError(RuntimeError):
@@ -37,12 +38,14 @@ class xy_obs(ctypes.Structure):
     _fields_ = [("sweep", ctypes.c_uint64), ("beta", ctypes.c_double), ("E", ctypes.c_double),
                 ("m2", ctypes.c_double), ("ex", ctypes.c_double), ("sx", ctypes.c_double),
                 ("ey", ctypes.c_double), ("sy", ctypes.c_double), ("ups_x", ctypes.c_double),
-                ("mk2", ctypes.c_double), ("near_ties", ctypes.c_uint64)]
+                ("mk2", ctypes.c_double), ("near_ties", ctypes.c_uint64), ("wrap", ctypes.c_uint64),
+                ("perc", ctypes.c_double)]
 
 
 class xy_pcc(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int64), ("dbeta0", ctypes.c_double), ("dbeta_min", ctypes.c_double),
-                ("halve_every", ctypes.c_int64), ("target", ctypes.c_double)]
+                ("halve_every", ctypes.c_int64), ("target", ctypes.c_double), ("rule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class xy_views(ctypes.Structure):
@@ -53,7 +56,8 @@ class xy_views(ctypes.Structure):
 
 OBS_DTYPE = np.dtype([("sweep", np.uint64), ("beta", np.float64), ("E", np.float64), ("m2", np.float64),
                       ("ex", np.float64), ("sx", np.float64), ("ey", np.float64), ("sy", np.float64),
-                      ("ups_x", np.float64), ("mk2", np.float64), ("near_ties", np.uint64)])
+                      ("ups_x", np.float64), ("mk2", np.float64), ("near_ties", np.uint64), ("wrap", np.uint64),
+                      ("perc", np.float64)])
 assert OBS_DTYPE.itemsize == ctypes.sizeof(xy_obs)
 
 _lib = None

@@ -298,6 +298,8 @@ struct xy_handle {
     std::vector<hipEvent_t> ev_pool;
     double ms[XY_K_COUNT] = {};
     int64_t launches[XY_K_COUNT] = {};
+    // wrapping-check buffers of the percolation rule (allocated on first use)
+    char *perc_mem = nullptr;
     // captured sweep sequence (xy_sweep_graph)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -411,6 +413,46 @@ int read_state(xy_handle *h, int32_t rep, xy::RepState *out)
 {
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     HIPCHECK(h, hipMemcpy(out, h->d_state + rep, sizeof *out, hipMemcpyDeviceToHost));
+    return XY_OK;
+}
+
+// Buffers of the wrapping check for every replica (two forest copies and two
+// arrays of per-node potentials), allocated on the first percolation-rule call
+// and named in the replicas' descriptors from then on.
+int ensure_wrap_buffers(xy_handle *h)
+{
+    if (h->perc_mem) return XY_OK;
+    const Plan &P = h->plan;
+    size_t total = 0;
+    std::vector<size_t> off(P.n);
+    for (int32_t k = 0; k < P.n; ++k) {
+        const Resolved &r = P.res[k];
+        if (r.L > xy::kWrapMaxL)
+            return fail(XY_EINVAL, "replica %d: the percolation rule needs L <= %lld (L=%lld)", k,
+                        (long long)xy::kWrapMaxL, (long long)r.L);
+        off[k] = total;
+        total += align_up(4 * (size_t)r.ntiles * r.nb * sizeof(unsigned long long));
+    }
+    char *mem = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&mem), total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(XY_ENOMEM, "hipMalloc of %zu bytes for the wrapping check failed: %s", total,
+                    hipGetErrorString(e));
+    }
+    for (int32_t k = 0; k < P.n; ++k) {
+        const size_t words = (size_t)P.res[k].ntiles * P.res[k].nb;
+        unsigned long long *w = reinterpret_cast<unsigned long long *>(mem + off[k]);
+        h->reps[k].node_cut[0] = w;
+        h->reps[k].node_cut[1] = w + words;
+        h->reps[k].pstate[0] = w + 2 * words;
+        h->reps[k].pstate[1] = w + 3 * words;
+    }
+    h->perc_mem = mem;
+    // the stream may still run sweeps that read the descriptors: copy in order
+    HIPCHECK(h, hipMemcpyAsync(h->d_reps, h->reps.data(), P.n * sizeof(xy::RepDesc), hipMemcpyHostToDevice,
+                               h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
     return XY_OK;
 }
 
@@ -549,6 +591,7 @@ int xy_free(xy_handle *h)
     for (auto &e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->perc_mem) (void)hipFree(h->perc_mem);
     if (h->own_arena && h->arena) (void)hipFree(h->arena);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -633,6 +676,12 @@ int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_me
     if (!(c->dbeta0 > 0.0) || !(c->dbeta_min >= 0.0) || c->halve_every < 0 || !std::isfinite(c->target))
         return fail(XY_EINVAL, "bad PCC schedule (dbeta0=%g dbeta_min=%g halve_every=%lld target=%g)",
                     c->dbeta0, c->dbeta_min, (long long)c->halve_every, c->target);
+    if (c->rule != XY_PCC_HELICITY && c->rule != XY_PCC_PERCOLATION)
+        return fail(XY_EINVAL, "PCC rule %d unknown", c->rule);
+    if (c->rule == XY_PCC_PERCOLATION) {
+        rc = ensure_wrap_buffers(h);
+        if (rc) return rc;
+    }
     const int32_t n = h->plan.n;
     Pipe pp;
     for (int64_t k = 0; k < nsteps; ++k) {
@@ -643,6 +692,7 @@ int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_me
             fa.dbeta_min = c->dbeta_min;
             fa.halve_every = c->halve_every;
             fa.target = c->target;
+            fa.rule = c->rule;
             if (window_mean) {
                 fa.wmean = h->d_wmean;
                 fa.wrow = k % kTraceChunk;

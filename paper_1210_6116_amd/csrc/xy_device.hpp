@@ -139,8 +139,9 @@ struct RepState {
     double dir[2][2];        // mirror direction of sweep t in slot t&1
     unsigned long long ties[2];  // near ties of sweep t in slot t&1
     uint32_t fin_done;       // chunks finalised in the running finalisation launch
-    uint32_t pad0;
-    double acc[9];           // PCC window sums: E, m2, ex, sx, ey, sy, ups_x, N sx^2, mk2
+    uint32_t wrap_acc;       // union of the wrap bits of the running PCC window
+    uint32_t wrap[2];        // wrap bits of sweep tl in slot tl&1 (4 | x | 2y; percolation rule only)
+    double acc[10];          // PCC window sums: E, m2, ex, sx, ey, sy, ups_x, N sx^2, mk2, wrapping indicator
     int64_t acc_n;           // sweeps in the running window
     int64_t pcc_k;           // PCC steps taken (halving schedule)
     uint64_t ties_total;
@@ -178,6 +179,12 @@ struct RepDesc {
     double *partials;        // kNumSums planes of per-tile sums: partials[k * ntiles + tile]
     double *partials2;       // chunk sums of the partials, fin_chunks x kNumSums
     double *fourier;         // cos(2 pi x / L), sin(2 pi x / L) at [2x], [2x+1], x = 0 .. L-1
+    // wrapping check (percolation rule; null unless the handle allocated it):
+    // node_cut[d] a copy of the forest merged without the links that cross the
+    // lattice's seam along x (d = 0) or y (d = 1); pstate[d] per forest node
+    // (component label << 32) | (potential + 2^31) of the check
+    unsigned long long *node_cut[2];
+    unsigned long long *pstate[2];
     RepState *st;
     int64_t L, N;
     int64_t ntiles, tile_base;  // tiles of this replica, first global tile id

@@ -208,6 +208,8 @@ int xy_group_create(size_t budget_bytes, int32_t max_slots, const xy_pcc *c, voi
     if (budget_bytes < (1u << 20)) return fail(XY_EINVAL, "budget of %zu bytes is too small", budget_bytes);
     if (c->window < 1 || !(c->dbeta0 > 0.0) || !(c->dbeta_min >= 0.0) || c->halve_every < 0)
         return fail(XY_EINVAL, "bad PCC rule");
+    if (c->rule != XY_PCC_HELICITY)
+        return fail(XY_EINVAL, "serving groups run the helicity-modulus PCC rule only (rule %d)", c->rule);
     xy_group *g = new (std::nothrow) xy_group;
     if (!g) return fail(XY_ENOMEM, "host allocation failed");
     g->pcc = *c;

@@ -85,8 +85,24 @@ hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int
         e = timer(XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, s); });
         if (e != hipSuccess) return e;
     }
+    // percolation rule: the wrapping check of the sweep just labelled (forest
+    // copies before the merge, their merges without the seam links after it)
+    const bool perc = fa.rule == XY_PCC_PERCOLATION;
+    if (perc) {
+        e = timer(XY_K_WRAP, [&] { return xy::launch_copy_nodes(lc, s); });
+        if (e != hipSuccess) return e;
+    }
     e = timer(XY_K_MERGE, [&] { return xy::launch_merge(lc, true, pp.fin_pending, s); });
     if (e != hipSuccess) return e;
+    if (perc) {
+        e = timer(XY_K_WRAP, [&] {
+            hipError_t e2 = xy::launch_merge_cut(lc, 1, s);
+            if (e2 == hipSuccess) e2 = xy::launch_merge_cut(lc, 2, s);
+            if (e2 == hipSuccess) e2 = xy::launch_wrap(lc, s);
+            return e2;
+        });
+        if (e != hipSuccess) return e;
+    }
     e = timer(XY_K_COINS, [&] { return xy::launch_resolve(lc, pp.fin_pending ? &pp.fa_pending : nullptr, s); });
     if (e != hipSuccess) return e;
     pp.fin_pending = false;

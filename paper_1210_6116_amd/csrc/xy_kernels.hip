@@ -974,9 +974,13 @@ __device__ __forceinline__ void fin_chunk(const RepDesc *__restrict__ reps, cons
                                           int32_t nrep, int64_t b, double *red);
 __device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red);
 
+// cut 0: the sweep's forest.  cut 1 / 2 (wrapping check): the copy node_cut[0]
+// / node_cut[1] of the forest, merged without the links that cross the
+// lattice's seam along x (right edges of the last tile column) / along y
+// (bottom edges of the last tile row).
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge(
     const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, const uint32_t *__restrict__ fin_rep,
-    int32_t nrep, int64_t gtile0, int64_t gtile_end, int32_t next_dir, int64_t nfin)
+    int32_t nrep, int64_t gtile0, int64_t gtile_end, int32_t next_dir, int64_t nfin, int32_t cut)
 {
     // the first nfin blocks: deferred finalisation, stage 1 (chunk c of
     // replica r; first in the grid, so that they overlap the unions)
@@ -1007,7 +1011,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
         b = (uint32_t)(nt * NB) + bsl[nt * NB + pn];
     }
     const uint64_t m = gmem(R.cross)[2 * lt + edge];
-    const bool on = lane < nlinks && ((m >> lane) & 1ull);
+    const bool seam = (cut == 1 && edge == 0 && T.tx == T.ntx - 1) || (cut == 2 && edge == 1 && T.ty == T.nty - 1);
+    const bool on = !seam && lane < nlinks && ((m >> lane) & 1ull);
     // one union per distinct pair of the wave: the lowest lane holding a pair
     // not seen yet leads it, and every lane with the same pair drops out
     uint64_t todo = __ballot(on && a != b);
@@ -1018,7 +1023,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
         lead = lead || lane == l;
         todo &= ~__ballot(on && a == la && b == lb);
     }
-    if (lead) union_nodes(gmem(R.node), a, b);
+    if (lead) union_nodes(gmem(cut == 0 ? R.node : R.node_cut[cut - 1]), a, b);
     // mirror direction of the sweep after the one labelled last
     if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, R.st->tl + 1);
 }
@@ -1122,6 +1127,150 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict_
     }
 }
 
+// ------------------------------------------------- wrapping check
+// Does some cluster of the sweep labelled last wind around the periodic
+// lattice?  Along x: cut the torus open along its x seam (the links from
+// column L-1 to column 0 removed: the forest copy merged with cut 1).  Every
+// cluster of the torus falls into clusters of the cut lattice ("sheets"), and
+// the seam links join sheets: link (L-1, y) -> (0, y) steps from the sheet of
+// its left end to the sheet of its right end, one column further along x.
+// Give every sheet a potential phi (unwrapped x offset in units of L) with
+// phi(right end's sheet) = phi(left end's sheet) + 1 along every active seam
+// link: a cluster winds along x exactly when some closed walk over sheets and
+// seam links crosses the seam a nonzero net number of times, i.e. when no
+// potentials satisfy every seam link of it.  The block propagates the
+// smallest sheet id of each cluster over the seam links together with the
+// potential it implies (a sheet takes both from a neighbour only when the id
+// is smaller than its own, so ids and potentials settle), then checks every
+// seam link.  Along y the same with cut 2 and the links (x, L-1) -> (x, 0).
+// First the forest copies, taken before the sweep's forest is merged; the
+// replica's wrap bits of the sweep start as 4 (checked).
+__global__ __launch_bounds__(kThreads) void k_copy_nodes(const RepDesc *__restrict__ reps,
+                                                          const uint32_t *__restrict__ tile_rep, int32_t nrep,
+                                                          int64_t gtile0)
+{
+    int64_t lt;
+    const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile0 + blockIdx.x, lt);
+    const int NB = R.nb;
+    const XY_G unsigned long long *src = gmem(R.node) + lt * NB;
+    XY_G unsigned long long *d0 = gmem(R.node_cut[0]) + lt * NB;
+    XY_G unsigned long long *d1 = gmem(R.node_cut[1]) + lt * NB;
+    for (int p = threadIdx.x; p < NB; p += kThreads) {
+        const unsigned long long v = src[p];
+        d0[p] = v;
+        d1[p] = v;
+    }
+    if (lt == 0 && threadIdx.x == 0) {
+        XY_G RepState *st = gmem(R.st);
+        st->wrap[st->tl & 1] = 4u;
+    }
+}
+
+// A check whose propagation found no settled state within its round limit
+// (cannot happen: every round with a change lowers some sheet's id) is
+// reported with bit 8 instead of looping on.
+constexpr uint32_t kWrapUnsettled = 8u;
+
+__global__ __launch_bounds__(kThreads) void k_wrap(const RepDesc *__restrict__ reps)
+{
+    const int d = blockIdx.x & 1;  // 0: along x, 1: along y
+    const RepDesc &R = reps[blockIdx.x >> 1];
+    __shared__ uint32_t ra[kWrapMaxL], rb[kWrapMaxL];  // sheets of the seam links' ends
+    __shared__ int changed, wound;
+    const int64_t L = R.L;
+    const int TW = R.TW, TH = R.TH, NB = R.nb, log2TW = R.log2TW, log2TH = __ffs(TH) - 1;
+    XY_G RepState *st = gmem(R.st);
+    const uint64_t tl = st->tl;
+    const XY_G uint8_t *bsl = gmem(R.bslot);
+    const XY_G unsigned long long *P = gmem(R.node_cut[d]);
+    XY_G unsigned long long *S = gmem(R.pstate[d]);
+    const XY_G uint32_t *plane = gmem(d == 0 ? R.bx[tl & 1] : R.by[tl & 1]);
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    constexpr uint32_t kBias = 0x80000000u;
+    // forest node of the edge position p of tile lt, followed to its root
+    auto sheet = [&](int64_t lt, int p) -> uint32_t {
+        uint32_t n = (uint32_t)(lt * NB) + bsl[lt * NB + p];
+        unsigned long long e = P[n];
+        while ((uint32_t)e != n) {
+            n = (uint32_t)e;
+            e = P[n];
+        }
+        return n;
+    };
+    for (int64_t j = threadIdx.x; j < L; j += kThreads) {
+        // the seam link from a = (xa, ya) to b = (xb, yb)
+        const int64_t xa = d == 0 ? L - 1 : j, ya = d == 0 ? j : L - 1;
+        const int64_t xb = d == 0 ? 0 : j, yb = d == 0 ? j : 0;
+        const int64_t ia = ya * L + xa;
+        uint32_t u = NONE, v = NONE;
+        if ((plane[ia >> 5] >> (ia & 31)) & 1u) {
+            const int64_t lta = (ya >> log2TH) * R.ntx + (xa >> log2TW);
+            const int64_t ltb = (yb >> log2TH) * R.ntx + (xb >> log2TW);
+            // a: right column / bottom row of its tile; b: left column / top row
+            const int pa = d == 0 ? 2 * TW + TH + (int)(ya & (TH - 1)) : TW + (int)(xa & (TW - 1));
+            const int pb = d == 0 ? 2 * TW + (int)(yb & (TH - 1)) : (int)(xb & (TW - 1));
+            u = sheet(lta, pa);
+            v = sheet(ltb, pb);
+        }
+        ra[j] = u;
+        rb[j] = v;
+    }
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < L; j += kThreads) {
+        if (ra[j] != NONE) {
+            S[ra[j]] = ((unsigned long long)ra[j] << 32) | kBias;
+            S[rb[j]] = ((unsigned long long)rb[j] << 32) | kBias;
+        }
+    }
+    auto sload = [&](uint32_t n) {
+        return __hip_atomic_load(&S[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    bool settled = false;
+    for (int64_t round = 0; round < 4 * L + 64; ++round) {
+        __syncthreads();
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        int mine = 0;
+        for (int64_t j = threadIdx.x; j < L; j += kThreads) {
+            const uint32_t u = ra[j], v = rb[j];
+            if (u == NONE) continue;
+            const unsigned long long su = sload(u), sv = sload(v);
+            const uint32_t lu = (uint32_t)(su >> 32), lv = (uint32_t)(sv >> 32);
+            // phi(v) = phi(u) + 1
+            if (lu < lv) {
+                const unsigned long long want = ((unsigned long long)lu << 32) | (uint32_t)((uint32_t)su + 1u);
+                unsigned long long expect = sv;
+                __hip_atomic_compare_exchange_strong(&S[v], &expect, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+                mine = 1;
+            } else if (lv < lu) {
+                const unsigned long long want = ((unsigned long long)lv << 32) | (uint32_t)((uint32_t)sv - 1u);
+                unsigned long long expect = su;
+                __hip_atomic_compare_exchange_strong(&S[u], &expect, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+                mine = 1;
+            }
+        }
+        if (mine) changed = 1;
+        __syncthreads();
+        if (!changed) {
+            settled = true;
+            break;
+        }
+    }
+    if (threadIdx.x == 0) wound = 0;
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < L; j += kThreads) {
+        const uint32_t u = ra[j], v = rb[j];
+        if (u == NONE) continue;
+        const unsigned long long su = sload(u), sv = sload(v);
+        if ((su >> 32) == (sv >> 32) && (uint32_t)sv != (uint32_t)su + 1u) wound = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicOr((uint32_t *)&st->wrap[tl & 1], (wound ? 1u << d : 0u) | (settled ? 0u : kWrapUnsettled));
+}
+
 // ------------------------------------------------- finalise a sweep
 // A replica's per-tile partials are summed in a fixed order (chunks of
 // kFinSpan tiles, then the chunks), and finish_sweep forms the observables,
@@ -1173,12 +1322,16 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
     if (measure_out) {
         o.sweep = t;
         o.near_ties = 0;
+        o.wrap = 0;
+        o.perc = -1.0;
         measure_out[R.idx] = o;
         return;
     }
     const int par = (int)(t & 1);
     o.sweep = t + 1;
     o.near_ties = st->ties[par];
+    o.wrap = fa.rule == XY_PCC_PERCOLATION ? st->wrap[par] : 0u;
+    o.perc = fa.rule == XY_PCC_PERCOLATION ? ((o.wrap & 3u) ? 1.0 : 0.0) : -1.0;
     st->ties_total += o.near_ties;
     st->ties[par] = 0ull;
     st->last = o;
@@ -1194,11 +1347,15 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
         acc[6] += o.ups_x;
         acc[7] += N * o.sx * o.sx;
         acc[8] += o.mk2;
+        acc[9] += o.perc;
+        st->wrap_acc |= (uint32_t)o.wrap;
         st->acc_n += 1;
         if (st->acc_n >= fa.window) {
             const double W = (double)fa.window;
             const double mean_ex = acc[2] / W, mean_ns2 = acc[7] / W;
-            const double bu = beta * (mean_ex - beta * mean_ns2);
+            // helicity rule: beta*Upsilon of the window; percolation rule: the
+            // fraction of its sweeps in which some cluster wound around the lattice
+            const double bu = fa.rule == XY_PCC_PERCOLATION ? acc[9] / W : beta * (mean_ex - beta * mean_ns2);
             double db = fa.dbeta0;
             if (fa.halve_every > 0) {
                 const int64_t halvings = st->pcc_k / fa.halve_every;
@@ -1219,13 +1376,16 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
                 m.ups_x = acc[6] / W;
                 m.mk2 = acc[8] / W;
                 m.near_ties = 0;
+                m.wrap = st->wrap_acc;
+                m.perc = acc[9] / W;
                 fa.wmean[fa.wrow * fa.nrep + R.idx] = m;
             }
             st->beta = nb;
             st->beta_sum += nb;
             st->beta_n += 1;
             st->pcc_k += 1;
-            for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+            for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+            st->wrap_acc = 0u;
             st->acc_n = 0;
         }
     }
@@ -1434,7 +1594,29 @@ hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s
     const int64_t nfin = fin ? lc.nfin : 0;
     const dim3 grid((unsigned)(xcd_pad(nfin) + nblk)), block(kThreads);
     hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.fin_rep, lc.nrep, lc.gtile0,
-                       lc.gtile_end, (int32_t)next_dir, nfin);
+                       lc.gtile_end, (int32_t)next_dir, nfin, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_cut(const Launch &lc, int cut, hipStream_t s)
+{
+    if (cut != 1 && cut != 2) return hipErrorInvalidValue;
+    const int64_t nblk = xcd_blocks(2 * (lc.gtile_end - lc.gtile0), kWaves);
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)nblk), dim3(kThreads), 0, s, lc.reps, lc.tile_rep, lc.fin_rep,
+                       lc.nrep, lc.gtile0, lc.gtile_end, 0, (int64_t)0, (int32_t)cut);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_nodes(const Launch &lc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_nodes, dim3((unsigned)(lc.gtile_end - lc.gtile0)), dim3(kThreads), 0, s, lc.reps,
+                       lc.tile_rep, lc.nrep, lc.gtile0);
+    return hipGetLastError();
+}
+
+hipError_t launch_wrap(const Launch &lc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_wrap, dim3((unsigned)(2 * lc.nrep)), dim3(kThreads), 0, s, lc.reps);
     return hipGetLastError();
 }
 

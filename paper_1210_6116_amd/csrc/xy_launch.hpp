@@ -32,7 +32,7 @@ struct FlipArgs {
     xy_obs *trace;        // device: trace[trace_row * nrep + replica], or null
     int64_t trace_row;
     int32_t nrep;
-    int32_t pad;
+    int32_t rule;         // XY_PCC_HELICITY, or XY_PCC_PERCOLATION (the sweep's wrapping check ran)
     int64_t window;       // PCC window (0: no PCC accumulation)
     double dbeta0, dbeta_min;
     int64_t halve_every;
@@ -50,6 +50,14 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s);
 // fin: also the first stage of the deferred finalisation of the previous,
 // fused sweep (the second runs with the edge coins, given its arguments).
 hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s);
+// Wrapping check of the sweep labelled last (percolation rule): copies of the
+// boundary forest before the merge (copy_nodes), merges of the copies without
+// the links across the x seam (cut 1) / the y seam (cut 2), then the check
+// itself (wrap) into every replica's state.
+hipError_t launch_copy_nodes(const Launch &lc, hipStream_t s);
+hipError_t launch_merge_cut(const Launch &lc, int cut, hipStream_t s);
+hipError_t launch_wrap(const Launch &lc, hipStream_t s);
+constexpr int64_t kWrapMaxL = 4096;  // largest side the wrapping check handles
 // Coins of the clusters at tile edges, after the merge; fin != null: the
 // second stage of a deferred finalisation.
 hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s);

@@ -140,11 +140,13 @@ def serve(trace, budget_bytes: int = 200 * 10 ** 9, max_slots: int = 64, pcc: xy
                              offered_updates=updates))
 
 
-def serve_sequential(trace, pcc: xy_pcc | None = None, clock=time.perf_counter, sleep=time.sleep, progress=None):
+def serve_sequential(trace, pcc: xy_pcc | None = None, clock=time.perf_counter, sleep=time.sleep, progress=None,
+                     deadline: float | None = None):
     """The same trace without batching: one request at a time in arrival order,
     each on its own plain handle (one lattice, the same PCC rule), started when
     it has arrived and the previous one has finished.  Same records and summary
-    as serve()."""
+    as serve().  deadline (a clock() value): no request is started after it;
+    the summary then covers the requests that ran (complete = False)."""
     from . import Lattices
 
     if pcc is None:
@@ -153,8 +155,12 @@ def serve_sequential(trace, pcc: xy_pcc | None = None, clock=time.perf_counter, 
     recs = {k: dict(trace[k]) for k in order}
     stream = torch.cuda.Stream()
     t0 = clock()
+    ran = []
     for done, k in enumerate(order):
+        if deadline is not None and clock() > deadline:
+            break
         r = recs[k]
+        ran.append(k)
         wait = r["arrival"] - (clock() - t0)
         if wait > 0:
             sleep(wait)
@@ -169,10 +175,12 @@ def serve_sequential(trace, pcc: xy_pcc | None = None, clock=time.perf_counter, 
         r.update(finished=done_t, ttc=done_t - r["arrival"], beta=beta, E=float(last["E"]), m2=float(last["m2"]))
         if progress is not None:
             progress(done + 1, len(order), done_t)
-    makespan = max(r["finished"] for r in recs.values()) - min(r["arrival"] for r in recs.values())
-    updates = sum(r["L"] * r["L"] * r["sweeps"] for r in recs.values())
-    ttc = np.array([r["ttc"] for r in recs.values()])
-    return dict(requests=[recs[k] for k in sorted(recs)],
-                summary=dict(n=len(recs), makespan_s=makespan, served_updates_per_s=updates / makespan,
+    done_recs = [recs[k] for k in ran]
+    makespan = max(r["finished"] for r in done_recs) - min(r["arrival"] for r in done_recs)
+    updates = sum(r["L"] * r["L"] * r["sweeps"] for r in done_recs)
+    ttc = np.array([r["ttc"] for r in done_recs])
+    return dict(requests=[recs[k] for k in sorted(ran)],
+                summary=dict(n=len(done_recs), complete=len(done_recs) == len(order), makespan_s=makespan,
+                             served_updates_per_s=updates / makespan,
                              ttc_p50_s=float(np.percentile(ttc, 50)), ttc_p99_s=float(np.percentile(ttc, 99)),
                              mean_running=1.0, offered_updates=updates))

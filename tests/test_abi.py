@@ -33,8 +33,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header():
     from paper_1210_6116_amd import _lib
     assert ctypes.sizeof(_lib.xy_params) == 40
-    assert ctypes.sizeof(_lib.xy_obs) == 88
-    assert ctypes.sizeof(_lib.xy_pcc) == 40
+    assert ctypes.sizeof(_lib.xy_obs) == 104
+    assert ctypes.sizeof(_lib.xy_pcc) == 48
 
 
 def test_bytes_required_and_argument_errors():
