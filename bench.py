@@ -241,10 +241,12 @@ def bench_batched(sweeps: int, nrep: int = 512):
     total = sum(sp["L"] ** 2 for sp in specs)
     # tile height picked by the autotuner for this replica set (timed here, not cached)
     rows, tune_s = autotune.tune(specs, use_cache=False)
+    merge, merge_s = autotune.tune_merge(specs, rows, use_cache=False)
     specs = [dict(sp, tile_rows=rows) for sp in specs]
     chunk = 10 if sweeps % 10 == 0 else 1
     stream = torch.cuda.Stream()
     bat = xy.Lattices(specs, stream=stream)
+    autotune.configure(bat, merge)
     bat.sweep_graph(chunk, 1)  # capture + warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -265,6 +267,8 @@ def bench_batched(sweeps: int, nrep: int = 512):
     del bat
     plain = [xy.Lattices(sp, stream=stream) for sp in specs]
     for lat in plain:
+        autotune.configure(lat, merge)
+    for lat in plain:
         lat.sweep(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -280,6 +284,8 @@ def bench_batched(sweeps: int, nrep: int = 512):
                         "each; batched = one handle replayed from a %d-sweep HIP graph; plain = one handle per "
                         "replica, swept one after another; both with the autotuned tile height" % (nrep, sweeps, chunk),
             "tile_rows": rows, "autotune_ms_per_sweep": {str(k): v * 1e3 for k, v in sorted(tune_s.items())},
+            "merge_schedule": {"dedup": merge[0], "edges_per_wave": merge[1],
+                               "ms_per_sweep": {"%d,%d" % k: v * 1e3 for k, v in sorted(merge_s.items())}},
             "round_sweeps": chunk, "round_ms_p50": percentile(rounds, 50), "round_ms_p99": percentile(rounds, 99),
             "spins": total, "batched_value": sweeps * total / dt_b, "plain_value": sweeps * total / dt_p,
             "unit": "spin updates/s", "speedup": dt_p / dt_b}
@@ -340,6 +346,9 @@ def main():
     ap.add_argument("--L", type=int, default=4096)
     ap.add_argument("--beta", type=float, default=1.12)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--merge-schedule", default="",
+                    help="'dedup,edges_per_wave' for the L = 4096 lattice instead of the autotuner's pick (counter "
+                         "runs, whose slowed kernels can rank the choices differently)")
     ap.add_argument("--cpu-sweeps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
     ap.add_argument("--no-instrument", action="store_true", help="skip the instrumented pass")
@@ -384,10 +393,18 @@ def main():
     seed = wl.SEED_L4096
     print("bench: L=%d beta=%g thermalisation=%d warmup=%d steps=%d" % (L, beta, THERM_SWEEPS, args.warmup,
                                                                       args.steps), file=sys.stderr, flush=True)
-    stream = torch.cuda.Stream()
-    lat = xy.Lattices(dict(L=L, beta=beta, seed=seed, tile_rows=args.tile_rows), stream=stream)
-    label_bits = 64 if N >= 2 ** 32 else 32
+    from paper_1210_6116_amd import autotune
+
     rows = args.tile_rows or 32
+    # merge schedule picked by the autotuner for this lattice (timed here, not cached)
+    if args.merge_schedule:
+        merge, merge_s = tuple(int(x) for x in args.merge_schedule.split(",")), {}
+    else:
+        merge, merge_s = autotune.tune_merge([dict(L=L, beta=beta, seed=seed)], rows, use_cache=False)
+    stream = torch.cuda.Stream()
+    lat = xy.Lattices(dict(L=L, beta=beta, seed=seed, tile_rows=rows), stream=stream)
+    autotune.configure(lat, merge)
+    label_bits = 64 if N >= 2 ** 32 else 32
 
     lat.sweep(THERM_SWEEPS)
     lat.sweep(args.warmup)
@@ -478,6 +495,8 @@ def main():
                                "warm-up sweeps untimed, %d timed sweeps" % (L, beta, label_bits, THERM_SWEEPS,
                                                                             args.warmup, args.steps),
                    "L": L, "beta": beta, "seed": seed, "thermalisation": THERM_SWEEPS,
+                   "merge_schedule": {"dedup": merge[0], "edges_per_wave": merge[1],
+                                      "tuned_ms_per_sweep": {"%d,%d" % k: v * 1e3 for k, v in sorted(merge_s.items())}},
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "valu_issue": valu_issue,

@@ -230,6 +230,18 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
 int xy_label_links_noalloc(int64_t L, int32_t label_bits, int32_t tile_rows, const uint32_t *d_bx,
                            const uint32_t *d_by, void *d_labels, void *hip_stream);
 
+/* Schedule of the merge across tile edges (tuning choices; results are
+ * identical bit for bit whatever they are).  dedup: every active link over a
+ * tile edge asks for the union of the boundary components at its two ends, and
+ * a wave of 64 such links often repeats a pair:
+ *   XY_DEDUP_WAVE       (default) one union per distinct pair of the wave;
+ *   XY_DEDUP_NEIGHBOUR  a link is skipped only when the link before it joins
+ *                       the same pair (fewer ballots when pairs rarely repeat).
+ * edges_per_wave: 1 (default) or 2 tile edges united one after the other by
+ * each wave (half as many waves).  XY_EINVAL for other values. */
+enum { XY_DEDUP_WAVE = 0, XY_DEDUP_NEIGHBOUR = 1 };
+int xy_set_merge(xy_handle *h, int32_t dedup, int32_t edges_per_wave);
+
 /* Per-kernel timing with HIP events on the handle's stream: enable (1) or
  * disable (0) recording; read the accumulated milliseconds and launch counts
  * of each kernel class (XY_K_*) and reset them (synchronizes).  XY_K_SWEEP
@@ -245,7 +257,9 @@ enum {
     XY_K_COINS = 5,    /* coins of the clusters at tile edges */
     XY_K_SWEEP = 6,
     XY_K_WRAP = 7,     /* wrapping check of the percolation rule (forest copies, cut merges, check) */
-    XY_K_COUNT = 8
+    XY_K_SPEC = 8,     /* flip of sweep t + links of sweep t+1 for both betas its PCC step may choose */
+    XY_K_PLSEL = 9,    /* labels of a sweep from the links of the chosen beta */
+    XY_K_COUNT = 10
 };
 int xy_timing(xy_handle *h, int32_t enable);
 int xy_timing_read(xy_handle *h, double *ms, int64_t *launches, double *samples, int64_t cap,

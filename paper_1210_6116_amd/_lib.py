@@ -17,9 +17,12 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxy.so")
 
 XY_OK, XY_EINVAL, XY_ENOMEM, XY_EDEVICE, XY_ESTATE, XY_EBUDGET = 0, -1, -2, -3, -4, -5
 XY_START_HOT, XY_START_COLD = 0, 1
-XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_FINALIZE, XY_K_COINS, XY_K_SWEEP, XY_K_WRAP, XY_K_COUNT = range(9)
-KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize", "coins", "sweep", "wrap")
+(XY_K_BONDS, XY_K_MERGE, XY_K_FLIP, XY_K_FUSED, XY_K_FINALIZE, XY_K_COINS, XY_K_SWEEP, XY_K_WRAP, XY_K_SPEC,
+ XY_K_PLSEL, XY_K_COUNT) = range(11)
+KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize", "coins", "sweep", "wrap", "flip_links2",
+                "labels_chosen")
 XY_PCC_HELICITY, XY_PCC_PERCOLATION = 0, 1
+XY_DEDUP_WAVE, XY_DEDUP_NEIGHBOUR = 0, 1
 
 
 class XYError(RuntimeError):
@@ -86,6 +89,7 @@ _SIGS = {
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "xy_label_links_noalloc": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "xy_set_merge": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "xy_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "xy_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_int64, _P(ctypes.c_int64)]),
@@ -215,6 +219,10 @@ def xy_label_links(L: int, label_bits: int, tile_rows: int, d_bx: int, d_by: int
 def xy_label_links_noalloc(L: int, label_bits: int, tile_rows: int, d_bx: int, d_by: int, d_labels: int,
                            stream=None):
     _check(load().xy_label_links_noalloc(L, label_bits, tile_rows, d_bx, d_by, d_labels, stream))
+
+
+def xy_set_merge(h, dedup: int, edges_per_wave: int):
+    _check(load().xy_set_merge(h, int(dedup), int(edges_per_wave)))
 
 
 def xy_timing(h, enable: bool):

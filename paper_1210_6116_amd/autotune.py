@@ -1,5 +1,8 @@
-"""Tile-height autotuner: times the sweep of a given replica set on the device
-for each tile height (64 x 16, 64 x 32, 64 x 64 tiles) and keeps the fastest.
+"""Autotuner of the sweep's shape choices, timed on the device for a given
+replica set: the tile height (64 x 16, 64 x 32, 64 x 64 tiles; tune), then
+the merge schedule (tune_merge): the merge's pair deduplication and the tile
+edges each of its waves unites.  None of the choices changes a result, only
+the speed.
 
 Results are cached as JSON (keyed by the replica sizes, the label width and the
 GPU architecture) under $XDG_CACHE_HOME/xymc (default ~/.cache/xymc).
@@ -72,3 +75,63 @@ def tune(specs, sweeps: int = 20, warmup: int = 5, use_cache: bool = True):
     except OSError:
         pass
     return best, timings
+
+
+def merge_candidates():
+    """The merge schedules timed: (pair deduplication, tile edges per wave)."""
+    from . import _lib
+
+    return [(dd, epw) for dd in (_lib.XY_DEDUP_WAVE, _lib.XY_DEDUP_NEIGHBOUR) for epw in (1, 2)]
+
+
+def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: int = 3, use_cache: bool = True):
+    """((dedup, edges per wave) fastest for these replicas at this tile height,
+    {(dedup, edges per wave): seconds per sweep}); cached like the tile height.
+
+    The choices are timed on one handle, thermalised by `warmup` sweeps first
+    (the forest's shape, and with it the merge and the edge coins, depends on
+    the state: a hot start ranks the choices differently), switching the
+    schedule between blocks of `sweeps` sweeps, `repeats` rounds over all
+    choices; a choice's time is its fastest block."""
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = _key(specs, arch) + "/rows%d/merge" % rows
+    path = _cache_path()
+    cache = {}
+    if os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        rec = cache[key]
+        timings = {tuple(int(x) for x in k.split(",")): v * 1e-3 for k, v in rec["ms_per_sweep"].items()}
+        return (int(rec["dedup"]), int(rec["edges_per_wave"])), timings
+    from . import Lattices
+
+    lat = Lattices([dict(s, tile_rows=rows) for s in specs])
+    lat.sweep(warmup)
+    timings = {}
+    for _ in range(repeats):
+        for choice in merge_candidates():
+            configure(lat, choice)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lat.sweep(sweeps)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / sweeps
+            timings[choice] = min(dt, timings.get(choice, dt))
+    lat.close()
+    best = min(timings, key=timings.get)
+    cache[key] = dict(dedup=best[0], edges_per_wave=best[1],
+                      ms_per_sweep={"%d,%d" % k: v * 1e3 for k, v in timings.items()})
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        json.dump(cache, open(path, "w"), indent=1)
+    except OSError:
+        pass
+    return best, timings
+
+
+def configure(lat, choice):
+    """Applies a (dedup, edges per wave) choice of tune_merge to a handle."""
+    lat.set_merge(choice[0], choice[1])

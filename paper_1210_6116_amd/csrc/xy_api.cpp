@@ -127,6 +127,12 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
             l.by[q] = off;
             off = align_up(off + words * 4);
         }
+        // the second candidate's link planes (a flip that activates the next
+        // sweep's links for both betas its PCC step may choose)
+        l.bxs = off;
+        off = align_up(off + words * 4);
+        l.bys = off;
+        off = align_up(off + words * 4);
         l.lab = off;
         off = align_up(off + (size_t)r.N * sizeof(uint16_t));
         l.bslot = off;
@@ -172,6 +178,8 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
         d.by[q] = reinterpret_cast<uint32_t *>(A + l.by[q]);
         d.edge[q] = reinterpret_cast<float2 *>(A + l.edge[q]);
     }
+    d.bxs = reinterpret_cast<uint32_t *>(A + l.bxs);
+    d.bys = reinterpret_cast<uint32_t *>(A + l.bys);
     d.lab = reinterpret_cast<uint16_t *>(A + l.lab);
     d.bslot = reinterpret_cast<uint8_t *>(A + l.bslot);
     d.node = reinterpret_cast<unsigned long long *>(A + l.node);
@@ -300,10 +308,13 @@ struct xy_handle {
     int64_t launches[XY_K_COUNT] = {};
     // wrapping-check buffers of the percolation rule (allocated on first use)
     char *perc_mem = nullptr;
+    int32_t dedup = XY_DEDUP_WAVE;  // merge's pair deduplication and edges per wave (xy_set_merge)
+    int32_t merge_epw = 1;
     // captured sweep sequence (xy_sweep_graph)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int64_t graph_n = 0;
+    int32_t graph_merge = 1;  // the merge choices the graph was captured with
 };
 
 namespace {
@@ -342,6 +353,8 @@ xy::Launch launch_all(xy_handle *h)
     lc.gtile_end = h->plan.total_tiles;
     lc.fin_rep = h->d_fin_rep;
     lc.nfin = h->plan.total_fin;
+    lc.dedup = h->dedup;
+    lc.merge_epw = h->merge_epw;
     return lc;
 }
 
@@ -352,7 +365,10 @@ hipError_t take_event(xy_handle *h, hipEvent_t *e)
         h->ev_pool.pop_back();
         return hipSuccess;
     }
-    return hipEventCreate(e);
+    // timing events only: no system-scope fence (cache writeback and
+    // invalidation) when they are recorded, so that they bracket the kernels
+    // alone; they are read after the stream has been synchronised
+    return hipEventCreateWithFlags(e, hipEventDisableSystemFence);
 }
 
 // Runs `launch` bracketed by timing events when timing is on.
@@ -380,7 +396,7 @@ hipError_t timed(xy_handle *h, int kind, F launch)
 // labels the links of the next one, and its finalisation runs with the next
 // sweep's edge coins (allowed only when beta cannot change in between, i.e.
 // not at the end of a PCC window, and only if another sweep follows).
-int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, Pipe &pp)
+int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, int next, Pipe &pp)
 {
     const xy::Launch lc = launch_all(h);
     hipEvent_t sweep_begin = nullptr;
@@ -389,7 +405,7 @@ int enqueue_sweep(xy_handle *h, const xy::FlipArgs &fa, bool fuse_next, Pipe &pp
         HIPCHECK(h, hipEventRecord(sweep_begin, h->stream));
     }
     auto timer = [&](int kind, auto launch) { return timed(h, kind, launch); };
-    HIPCHECK(h, enqueue_sweep_lc(lc, h->d_reps, h->plan.n, fa, fuse_next, pp, h->stream, timer));
+    HIPCHECK(h, enqueue_sweep_lc(lc, h->d_reps, h->plan.n, fa, next, pp, h->stream, timer));
     if (h->timing) {
         xy_handle::Ev ev;
         ev.kind = XY_K_SWEEP;
@@ -614,7 +630,7 @@ int xy_sweep(xy_handle *h, int64_t nsweeps, xy_obs *trace)
         // a sweep whose trace row is copied back right after it is not fused
         // (its finalisation must not be deferred past the copy)
         const bool fuse = k + 1 < nsweeps && !(trace && fa.trace_row == kTraceChunk - 1);
-        rc = enqueue_sweep(h, fa, fuse, pp);
+        rc = enqueue_sweep(h, fa, fuse ? NEXT_FUSE : NEXT_END, pp);
         if (rc) return rc;
         if (trace && (fa.trace_row == kTraceChunk - 1 || k == nsweeps - 1)) {
             const int64_t first = k - fa.trace_row;
@@ -633,14 +649,15 @@ int xy_sweep_graph(xy_handle *h, int64_t nsweeps, int64_t replays)
     if (nsweeps < 1 || replays < 0)
         return fail(XY_EINVAL, "nsweeps=%lld replays=%lld", (long long)nsweeps, (long long)replays);
     if (h->timing) return fail(XY_ESTATE, "per-kernel timing is on; graphs capture no events");
-    if (!h->graph_exec || h->graph_n != nsweeps) {
+    if (!h->graph_exec || h->graph_n != nsweeps || h->graph_merge != h->dedup * 4 + h->merge_epw) {
         if (h->graph_exec) HIPCHECK(h, hipGraphExecDestroy(h->graph_exec));
         if (h->graph) HIPCHECK(h, hipGraphDestroy(h->graph));
         h->graph_exec = nullptr;
         h->graph = nullptr;
         HIPCHECK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
         Pipe pp;
-        for (int64_t k = 0; k < nsweeps && rc == XY_OK; ++k) rc = enqueue_sweep(h, no_pcc(h), k + 1 < nsweeps, pp);
+        for (int64_t k = 0; k < nsweeps && rc == XY_OK; ++k)
+            rc = enqueue_sweep(h, no_pcc(h), k + 1 < nsweeps ? NEXT_FUSE : NEXT_END, pp);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(h->stream, &graph);
         if (rc) return rc;
@@ -648,6 +665,7 @@ int xy_sweep_graph(xy_handle *h, int64_t nsweeps, int64_t replays)
         h->graph = graph;
         HIPCHECK(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
         h->graph_n = nsweeps;
+        h->graph_merge = h->dedup * 4 + h->merge_epw;
     }
     for (int64_t r = 0; r < replays; ++r) HIPCHECK(h, hipGraphLaunch(h->graph_exec, h->stream));
     return XY_OK;
@@ -697,7 +715,9 @@ int xy_pcc_step(xy_handle *h, const xy_pcc *c, int64_t nsteps, xy_obs *window_me
                 fa.wmean = h->d_wmean;
                 fa.wrow = k % kTraceChunk;
             }
-            rc = enqueue_sweep(h, fa, w + 1 < c->window, pp);
+            // inside a window beta cannot change: fuse; at its end the step
+            // moves beta by +-dbeta: activate the next sweep's links for both
+            rc = enqueue_sweep(h, fa, w + 1 < c->window ? NEXT_FUSE : (k + 1 < nsteps ? NEXT_SPEC : NEXT_END), pp);
             if (rc) return rc;
         }
         const int64_t row = k % kTraceChunk;
@@ -883,6 +903,19 @@ int xy_label_links(int64_t L, int32_t label_bits, int32_t tile_rows, const uint3
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(mem);
     if (e != hipSuccess) return fail(XY_EDEVICE, "labelling failed: %s", hipGetErrorString(e));
+    return XY_OK;
+}
+
+int xy_set_merge(xy_handle *h, int32_t dedup, int32_t edges_per_wave)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (dedup != XY_DEDUP_WAVE && dedup != XY_DEDUP_NEIGHBOUR)
+        return fail(XY_EINVAL, "merge deduplication policy %d unknown", dedup);
+    if (edges_per_wave != 1 && edges_per_wave != 2)
+        return fail(XY_EINVAL, "edges_per_wave=%d is not 1 or 2", edges_per_wave);
+    h->dedup = dedup;
+    h->merge_epw = edges_per_wave;
     return XY_OK;
 }
 

@@ -142,6 +142,8 @@ struct RepState {
     uint32_t wrap_acc;       // union of the wrap bits of the running PCC window
     uint32_t wrap[2];        // wrap bits of sweep tl in slot tl&1 (4 | x | 2y; percolation rule only)
     double acc[10];          // PCC window sums: E, m2, ex, sx, ey, sy, ups_x, N sx^2, mk2, wrapping indicator
+    double beta_cand;        // the first of the two betas a flip with both candidates' links activated
+    unsigned long long ties_spec[2];  // near ties of those links, per candidate
     int64_t acc_n;           // sweeps in the running window
     int64_t pcc_k;           // PCC steps taken (halving schedule)
     uint64_t ties_total;
@@ -171,6 +173,7 @@ struct RepDesc {
     float *c, *s;            // spin planes, N floats each
     uint16_t *lab;           // tile-local labels
     uint32_t *bx[2], *by[2]; // active-link bit planes of sweep t in slot t&1
+    uint32_t *bxs, *bys;     // the second beta's candidate planes (flip with both candidates' links)
     uint8_t *bslot;          // edge positions -> slot
     unsigned long long *node;     // boundary-component forest
     unsigned long long *cross;    // links over the right / bottom tile edges

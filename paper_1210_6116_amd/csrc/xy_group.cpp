@@ -311,10 +311,11 @@ int xy_group_round(xy_group *g, int64_t max_sweeps, int64_t *ran)
     for (int64_t j = 0; j < k; ++j) {
         // the next sweep's links may be activated in this pass only if no
         // running request ends a PCC window (and so changes beta) here
-        bool fuse = j + 1 < k;
+        bool window_ends = false;
         for (int32_t s : g->order)
-            if ((g->slots[s].done + j + 1) % g->pcc.window == 0) fuse = false;
-        GCHECK(g, enqueue_sweep_lc(g->lc, g->d_reps, n, fa, fuse, pp, g->stream, plain));
+            if ((g->slots[s].done + j + 1) % g->pcc.window == 0) window_ends = true;
+        const int next = j + 1 < k ? (window_ends ? NEXT_SPEC : NEXT_FUSE) : NEXT_END;
+        GCHECK(g, enqueue_sweep_lc(g->lc, g->d_reps, n, fa, next, pp, g->stream, plain));
     }
     GCHECK(g, hipStreamSynchronize(g->stream));
     for (int32_t s : g->order) {

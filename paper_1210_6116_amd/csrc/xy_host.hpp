@@ -31,7 +31,7 @@ struct Resolved {
 
 // Per-replica byte layout inside an arena.
 struct RepLayout {
-    size_t c, s, lab, bx[2], by[2], bslot, node, cross, edge[2], ecoin, partials, partials2, fourier, end;
+    size_t c, s, lab, bx[2], by[2], bxs, bys, bslot, node, cross, edge[2], ecoin, partials, partials2, fourier, end;
 };
 
 struct Plan {
@@ -67,24 +67,36 @@ struct Pipe {
     bool ready = false;        // the links of the next sweep are activated and labelled
     bool fin_pending = false;  // the last flip's finalisation is still to run
     xy::FlipArgs fa_pending;   // its arguments
+    bool spec = false;         // the last flip activated the next sweep's links for both candidate betas
 };
 
-// One sweep of every replica in lc: links + tile labels (unless pp.ready),
-// merge of the boundary components (with the deferred finalisation of the
-// previous sweep), edge coins, then either the flip and its
-// finalisation, or (fuse_next) the flip fused with the next sweep's links,
-// whose finalisation runs with the next sweep's edge coins.  A sequence must
-// end with fuse_next = false.  timer(kind, launch) runs each launch (and may
-// bracket it with events).
+// What the flip of a sweep does besides flipping: END the sequence (flip,
+// finalisation); FUSE the links and labels of the next sweep into it (beta
+// cannot change in between); SPEC activate the next sweep's links for both
+// betas the PCC step after this sweep may choose (the next sweep labels the
+// links of the chosen one instead of activating them from the spins again).
+enum { NEXT_END = 0, NEXT_FUSE = 1, NEXT_SPEC = 2 };
+
+// One sweep of every replica in lc: links + tile labels (unless pp.ready; from
+// the chosen candidate's planes if pp.spec), merge of the boundary components
+// (with the deferred finalisation of the previous sweep), edge coins, then the
+// flip as `next` says: with its finalisation (END, SPEC), or fused with the
+// next sweep's links, whose finalisation runs with the next sweep's merge and
+// edge coins (FUSE).  A sequence must end with NEXT_END.  timer(kind, launch)
+// runs each launch (and may bracket it with events).
 template <typename Timer>
 hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int32_t nrep, const xy::FlipArgs &fa,
-                            bool fuse_next, Pipe &pp, hipStream_t s, Timer &&timer)
+                            int next, Pipe &pp, hipStream_t s, Timer &&timer)
 {
     hipError_t e = hipSuccess;
     if (!pp.ready) {
-        e = timer(XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, s); });
+        if (pp.spec)
+            e = timer(XY_K_PLSEL, [&] { return xy::launch_tile(lc, xy::TILE_PLSEL, s); });
+        else
+            e = timer(XY_K_BONDS, [&] { return xy::launch_tile(lc, xy::TILE_BONDS, s); });
         if (e != hipSuccess) return e;
     }
+    pp.spec = false;
     // percolation rule: the wrapping check of the sweep just labelled (forest
     // copies before the merge, their merges without the seam links after it)
     const bool perc = fa.rule == XY_PCC_PERCOLATION;
@@ -106,17 +118,21 @@ hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int
     e = timer(XY_K_COINS, [&] { return xy::launch_resolve(lc, pp.fin_pending ? &pp.fa_pending : nullptr, s); });
     if (e != hipSuccess) return e;
     pp.fin_pending = false;
-    if (fuse_next) {
+    if (next == NEXT_FUSE) {
         e = timer(XY_K_FUSED, [&] { return xy::launch_tile(lc, xy::TILE_FUSED, s); });
         pp.ready = true;
         pp.fin_pending = true;
         pp.fa_pending = fa;
         return e;
     }
-    e = timer(XY_K_FLIP, [&] { return xy::launch_tile(lc, xy::TILE_FLIP, s); });
+    if (next == NEXT_SPEC)
+        e = timer(XY_K_SPEC, [&] { return xy::launch_tile(lc, xy::TILE_SPEC, s, &fa); });
+    else
+        e = timer(XY_K_FLIP, [&] { return xy::launch_tile(lc, xy::TILE_FLIP, s); });
     if (e != hipSuccess) return e;
     e = timer(XY_K_FINALIZE, [&] { return xy::launch_finalize(lc, fa, nullptr, s); });
     pp.ready = false;
+    pp.spec = next == NEXT_SPEC;
     return e;
 }
 

@@ -42,7 +42,7 @@ namespace xy {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-enum : int { M_BONDS = 0, M_FLIP = 1, M_FUSED = 2, M_PLANES = 3 };
+enum : int { M_BONDS = 0, M_FLIP = 1, M_FUSED = 2, M_PLANES = 3, M_SPEC = 4, M_PLSEL = 5 };
 
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ const RepDesc &rep_of(const RepDesc *__restrict__ reps,
@@ -438,11 +438,16 @@ template <typename IT, int MODE, int BT, int NW>
 // VGPRs; 64 x 32 tiles take 18 KB of LDS per block), 6 with 64-bit indices.
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(IT) == 4 ? 7 : 6))) void k_tile(
     const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, int32_t nrep, int64_t gtile0,
-    int64_t gtile_end)
+    int64_t gtile_end, FlipArgs fa)
 {
-    constexpr bool FLIP = MODE == M_FLIP || MODE == M_FUSED;
-    constexpr bool BONDS = MODE == M_BONDS || MODE == M_FUSED;
-    constexpr bool CCL = MODE != M_FLIP;
+    // M_SPEC: flip of sweep t and the links of sweep t+1 for both betas the
+    // PCC step after sweep t may choose, no labelling; M_PLSEL: labels of a
+    // sweep from the link planes of the beta that was chosen
+    constexpr bool FLIP = MODE == M_FLIP || MODE == M_FUSED || MODE == M_SPEC;
+    constexpr bool BONDS = MODE == M_BONDS || MODE == M_FUSED || MODE == M_SPEC;
+    constexpr bool CCL = MODE != M_FLIP && MODE != M_SPEC;
+    constexpr bool NEXT = MODE == M_FUSED || MODE == M_SPEC;    // activates the links of sweep t+1
+    constexpr bool FROM_PLANES = MODE == M_PLANES || MODE == M_PLSEL;
     constexpr bool FIXED = BT > 0;
     constexpr int BMAX = FIXED ? BT : 16;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -473,7 +478,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     // the sweep counter, so these loads overlap its read
     float c0[BMAX], s0[BMAX];
     uint32_t lv[BMAX];  // labels of the flipped sweep (flip modes)
-    if constexpr (MODE != M_PLANES) {
+    if constexpr (!FROM_PLANES) {
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             if (own(k)) {
@@ -483,20 +488,20 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                     const uint32_t i = woff(k, lane);
                     c0[k] = __builtin_nontemporal_load(&gel(cpw, i));
                     s0[k] = __builtin_nontemporal_load(&gel(spw, i));
-                    if constexpr (MODE == M_FLIP || MODE == M_FUSED)
+                    if constexpr (FLIP)
                         lv[k] = __builtin_nontemporal_load(&gel(gmem((const uint16_t *)R.lab) + T.base, i));
                 } else {
                     const IT i = T.site(yb + k, lane);
                     c0[k] = gel(cp, i);
                     s0[k] = gel(sp, i);
-                    if constexpr (MODE == M_FLIP || MODE == M_FUSED) lv[k] = gel(gmem((const uint16_t *)R.lab), i);
+                    if constexpr (FLIP) lv[k] = gel(gmem((const uint16_t *)R.lab), i);
                 }
             }
         }
     }
     const uint64_t t = cload(&R.st->t);
     const int par = (int)(t & 1);
-    const uint64_t tb = MODE == M_FUSED ? t + 1 : t;  // sweep whose links this launch activates
+    const uint64_t tb = NEXT ? t + 1 : t;  // sweep whose links this launch activates
     const int pb = (int)(tb & 1);
 
     // spin area: the spins with their halo; after the link pass the labelling's
@@ -507,6 +512,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     uint64_t *bym = bxm + TH;
     uint64_t *rcoin = bym + TH;   // TH words: coins of the tile's rows
     uint64_t *scoin = rcoin + TH; // 4 words: coins of the edge positions
+    uint64_t *bxm2 = scoin + 4;   // M_SPEC: the row masks of the second beta
+    uint64_t *bym2 = bxm2 + TH;
     uint32_t *lab_s = (uint32_t *)smem;  // after the link pass
     const int64_t ecount = TH + TW;
 
@@ -625,10 +632,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     double v[kPairSums] = {};
     double cs = 0.0, ss = 0.0;  // the lane's column sums of cos and sin
     // link masks of the wave's own rows, kept in scalar registers (fixed tiles)
-    constexpr bool RMASK = FIXED && BONDS;
+    constexpr bool RMASK = FIXED && BONDS && CCL;
+    bool two = false;  // M_SPEC: the PCC step after this sweep moves beta (two candidates)
     uint64_t xrow[RMASK ? BMAX : 1], yrow[RMASK ? BMAX : 1];
     if constexpr (FLIP || BONDS) {
-        BondCtx ctx;
+        BondCtx ctx, ctx2;
         uint32_t key0 = 0, key1 = 0;
         if constexpr (BONDS) {
             ctx.rx = cload(&R.st->dir[pb][0]);
@@ -636,12 +644,53 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
             ctx.beta = cload(&R.st->beta);
             ctx.rxf = (float)ctx.rx;
             ctx.ryf = (float)ctx.ry;
+            ctx.ties = (unsigned long long *)&st->ties[pb];
+            if constexpr (MODE == M_SPEC) {
+                // the PCC step at the end of this sweep's window moves beta by
+                // +-db (the finalisation's own expressions): links for both
+                // candidates, the first as beta + db (or beta if no step ends)
+                const double beta = ctx.beta;
+                if (fa.window > 0 && cload(&R.st->acc_n) + 1 >= fa.window) {
+                    double db = fa.dbeta0;
+                    if (fa.halve_every > 0) {
+                        const int64_t halvings = cload(&R.st->pcc_k) / fa.halve_every;
+                        db = ldexp(fa.dbeta0, -(int)(halvings < 200 ? halvings : 200));
+                    }
+                    if (db < fa.dbeta_min) db = fa.dbeta_min;
+                    two = true;
+                    ctx.beta = beta + db;
+                    ctx2 = ctx;
+                    ctx2.beta = beta + (-db);
+                    ctx2.bl = (float)(-2.0 * ctx2.beta * 1.4426950408889634);
+                    ctx2.gw = (float)(1e-5 * (1.0 + ctx2.beta) * 4294967296.0);
+                    ctx2.ties = (unsigned long long *)&st->ties_spec[1];
+                }
+                ctx.ties = (unsigned long long *)&st->ties_spec[0];
+                if (lt == 0 && threadIdx.x == 0) st->beta_cand = ctx.beta;
+            }
             ctx.bl = (float)(-2.0 * ctx.beta * 1.4426950408889634);
             ctx.gw = (float)(1e-5 * (1.0 + ctx.beta) * 4294967296.0);
-            ctx.ties = (unsigned long long *)&st->ties[pb];
             key0 = (uint32_t)R.seed;
             key1 = (uint32_t)(R.seed >> 32);
         }
+        // the decisions of one row of links for the betas of c: margins
+        // against the Philox words, the FP64 definition inside the guard band
+        auto decide = [&](const BondCtx &c, float bai, float pr, float pd, uint32_t wx, uint32_t wy, float2 a,
+                          float2 r, float2 d, uint64_t &mx, uint64_t &my) {
+            const float dx = bond_margin(bai, pr, wx);
+            const float dy = bond_margin(bai, pd, wy);
+            mx = __ballot(dx < 0.0f);
+            my = __ballot(dy < 0.0f);
+            if (__ballot(fabsf(dx) <= c.gw) | __ballot(fabsf(dy) <= c.gw)) {
+                // some lane inside the guard band (rare)
+                bool xa = dx < 0.0f, ya = dy < 0.0f;
+                if (fabsf(dx) <= c.gw) xa = bond_exact(a.x, a.y, r.x, r.y, c.rx, c.ry, c.beta, wx, c.ties);
+                if (fabsf(dy) <= c.gw) ya = bond_exact(a.x, a.y, d.x, d.y, c.rx, c.ry, c.beta, wy, c.ties);
+                mx = __ballot(xa);
+                my = __ballot(ya);
+            }
+        };
+        float padn = 0.0f;  // M_SPEC: projection of the row below
         U4 w = {0u, 0u, 0u, 0u};
         // a row's values below are the next row's own: carried, not recomputed
         double cdn = 0.0, sdn = 0.0;
@@ -651,6 +700,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
             const int y = yb + k;
             if (!FIXED && y >= TH) break;
             uint64_t mx = 0, my = 0;  // active links of the row (BONDS)
+            uint64_t mx2 = 0, my2 = 0;  // M_SPEC: for the second beta
             if (FIXED || lane < TW) {
                 const float2 a = spin[y * SS + lane];
                 const float2 r = spin[y * SS + lane + 1];
@@ -680,22 +730,18 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                     const bool odd = FIXED && BT % 2 == 0 ? (k & 1) : (gy & 1);
                     const uint32_t wx = odd ? w.z : w.x;
                     const uint32_t wy = odd ? w.w : w.y;
-                    const float bai = k == 0 ? ctx.bl * bond_proj(ctx, a) : badn;
-                    const float ad = bond_proj(ctx, d);
-                    badn = ctx.bl * ad;
-                    const float dx = bond_margin(bai, bond_proj(ctx, r), wx);
-                    const float dy = bond_margin(bai, ad, wy);
-                    mx = __ballot(dx < 0.0f);
-                    my = __ballot(dy < 0.0f);
-                    if (__ballot(fabsf(dx) <= ctx.gw) | __ballot(fabsf(dy) <= ctx.gw)) {
-                        // some lane inside the guard band (rare)
-                        bool xa = dx < 0.0f, ya = dy < 0.0f;
-                        if (fabsf(dx) <= ctx.gw)
-                            xa = bond_exact(a.x, a.y, r.x, r.y, ctx.rx, ctx.ry, ctx.beta, wx, ctx.ties);
-                        if (fabsf(dy) <= ctx.gw)
-                            ya = bond_exact(a.x, a.y, d.x, d.y, ctx.rx, ctx.ry, ctx.beta, wy, ctx.ties);
-                        mx = __ballot(xa);
-                        my = __ballot(ya);
+                    if constexpr (MODE == M_SPEC) {
+                        // projections shared by both betas
+                        const float pa = k == 0 ? bond_proj(ctx, a) : padn;
+                        const float pd = bond_proj(ctx, d), pr = bond_proj(ctx, r);
+                        padn = pd;
+                        decide(ctx, ctx.bl * pa, pr, pd, wx, wy, a, r, d, mx, my);
+                        if (two) decide(ctx2, ctx2.bl * pa, pr, pd, wx, wy, a, r, d, mx2, my2);
+                    } else {
+                        const float bai = k == 0 ? ctx.bl * bond_proj(ctx, a) : badn;
+                        const float ad = bond_proj(ctx, d);
+                        badn = ctx.bl * ad;
+                        decide(ctx, bai, bond_proj(ctx, r), ad, wx, wy, a, r, d, mx, my);
                     }
                 }
             }
@@ -703,6 +749,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                 if (lane == 0) {
                     bxm[y] = mx;
                     bym[y] = my;
+                    if constexpr (MODE == M_SPEC) {
+                        bxm2[y] = mx2;
+                        bym2[y] = my2;
+                    }
                 }
                 if constexpr (RMASK) {
                     xrow[k] = mx;
@@ -756,14 +806,91 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
             }
         }
     };
+    // active-link bit planes of sweep tb from the row masks in LDS
+    auto write_planes = [&](const uint64_t *xm, const uint64_t *ym, XY_G uint32_t *gbx, XY_G uint32_t *gby) {
+        if (TW == 64) {
+            for (int j = threadIdx.x; j < 2 * TH; j += NT) {
+                const int y = j >> 1, half = j & 1;
+                const IT word = (T.site(y, 0) >> 5) + (IT)half;
+                gbx[word] = (uint32_t)(xm[y] >> (32 * half));
+                gby[word] = (uint32_t)(ym[y] >> (32 * half));
+            }
+        } else {
+            // narrow lattice (L < 64): the tile spans whole rows, so whole words
+            const int nbits = TW * TH;
+            const int nwords = nbits >= 32 ? nbits >> 5 : 1;
+            for (int j = threadIdx.x; j < nwords; j += NT) {
+                uint32_t vx = 0u, vy = 0u;
+                for (int b = 0; b < 32; ++b) {
+                    const int p = j * 32 + b;
+                    if (p >= nbits) break;
+                    const int y = p >> T.log2TW, x = p & (TW - 1);
+                    vx |= (uint32_t)((xm[y] >> x) & 1ull) << b;
+                    vy |= (uint32_t)((ym[y] >> x) & 1ull) << b;
+                }
+                const IT word = (T.base >> 5) + (IT)j;
+                gbx[word] = vx;
+                gby[word] = vy;
+            }
+        }
+    };
     if constexpr (FLIP) {
         wave_sums<kPairSums>(v, red);
         if constexpr (!CCL) {
             __syncthreads();
             fold_link_sums();
+            if constexpr (MODE == M_SPEC) {
+                // the candidates' planes: the first in the slot of sweep t+1,
+                // the second (if the step can move beta) in the spare planes
+                write_planes(bxm, bym, gmem(R.bx[pb]), gmem(R.by[pb]));
+                if (two) write_planes(bxm2, bym2, gmem(R.bxs), gmem(R.bys));
+            }
             __syncthreads();
             fold_site_sums();
             return;
+        }
+    }
+    if constexpr (MODE == M_PLSEL) {
+        // the finalisation chose beta: the links of this sweep are the
+        // planes of the candidate it matches; the second candidate's planes
+        // are copied into the sweep's slot, and its near ties counted
+        const bool second = cload(&R.st->beta) != cload(&R.st->beta_cand);
+        XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
+        const XY_G uint32_t *sbx = second ? gmem((const uint32_t *)R.bxs) : gbx;
+        const XY_G uint32_t *sby = second ? gmem((const uint32_t *)R.bys) : gby;
+        if (TW == 64) {
+            for (int y = threadIdx.x; y < TH; y += NT) {
+                const IT word = T.site(y, 0) >> 5;
+                const uint32_t x0 = sbx[word], x1 = sbx[word + 1], y0 = sby[word], y1 = sby[word + 1];
+                bxm[y] = ((uint64_t)x1 << 32) | x0;
+                bym[y] = ((uint64_t)y1 << 32) | y0;
+                if (second) {
+                    gbx[word] = x0;
+                    gbx[word + 1] = x1;
+                    gby[word] = y0;
+                    gby[word + 1] = y1;
+                }
+            }
+        } else {
+            for (int y = threadIdx.x; y < TH; y += NT) {
+                uint64_t mx = 0, my = 0;
+                for (int x = 0; x < TW; ++x) {
+                    const IT i = T.site(y, x);
+                    mx |= (uint64_t)((sbx[i >> 5] >> (i & 31)) & 1u) << x;
+                    my |= (uint64_t)((sby[i >> 5] >> (i & 31)) & 1u) << x;
+                }
+                bxm[y] = mx;
+                bym[y] = my;
+            }
+            if (second) {
+                __syncthreads();  // (uniform: second is the same in every thread)
+                write_planes(bxm, bym, gbx, gby);
+            }
+        }
+        if (lt == 0 && threadIdx.x == 0) {
+            st->ties[pb] += st->ties_spec[second ? 1 : 0];
+            st->ties_spec[0] = 0ull;
+            st->ties_spec[1] = 0ull;
         }
     }
     if constexpr (MODE == M_PLANES) {
@@ -784,35 +911,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     __syncthreads();
     if constexpr (FLIP) fold_link_sums();
     const uint32_t NONE = 0xFFFFFFFFu;
-    if constexpr (BONDS) {
-        // active-link bit planes of sweep tb
-        XY_G uint32_t *gbx = gmem(R.bx[pb]), *gby = gmem(R.by[pb]);
-        if (TW == 64) {
-            for (int j = threadIdx.x; j < 2 * TH; j += NT) {
-                const int y = j >> 1, half = j & 1;
-                const IT word = (T.site(y, 0) >> 5) + (IT)half;
-                gbx[word] = (uint32_t)(bxm[y] >> (32 * half));
-                gby[word] = (uint32_t)(bym[y] >> (32 * half));
-            }
-        } else {
-            // narrow lattice (L < 64): the tile spans whole rows, so whole words
-            const int nbits = TW * TH;
-            const int nwords = nbits >= 32 ? nbits >> 5 : 1;
-            for (int j = threadIdx.x; j < nwords; j += NT) {
-                uint32_t vx = 0u, vy = 0u;
-                for (int b = 0; b < 32; ++b) {
-                    const int p = j * 32 + b;
-                    if (p >= nbits) break;
-                    const int y = p >> T.log2TW, x = p & (TW - 1);
-                    vx |= (uint32_t)((bxm[y] >> x) & 1ull) << b;
-                    vy |= (uint32_t)((bym[y] >> x) & 1ull) << b;
-                }
-                const IT word = (T.base >> 5) + (IT)j;
-                gbx[word] = vx;
-                gby[word] = vy;
-            }
-        }
-    }
+    if constexpr (BONDS) write_planes(bxm, bym, gmem(R.bx[pb]), gmem(R.by[pb]));
 
     // ---- in-tile labelling of sweep tb
     if (lt == 0 && threadIdx.x == 0) st->tl = tb;
@@ -978,22 +1077,12 @@ __device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa
 // / node_cut[1] of the forest, merged without the links that cross the
 // lattice's seam along x (right edges of the last tile column) / along y
 // (bottom edges of the last tile row).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge(
-    const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, const uint32_t *__restrict__ fin_rep,
-    int32_t nrep, int64_t gtile0, int64_t gtile_end, int32_t next_dir, int64_t nfin, int32_t cut)
+// The unions of tile edge gw (2 x tile + 0: right edge, + 1: bottom edge).
+template <int DEDUP, bool CUT>
+__device__ __forceinline__ void merge_edge(const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep,
+                                           int32_t nrep, int64_t gtile0, int64_t gw, int32_t next_dir, int32_t cut)
 {
-    // the first nfin blocks: deferred finalisation, stage 1 (chunk c of
-    // replica r; first in the grid, so that they overlap the unions)
-    if (blockIdx.x < nfin) {
-        __shared__ double red[kWaves * kNumSums];
-        fin_chunk(reps, fin_rep, nrep, blockIdx.x, red);
-        return;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (blockIdx.x < xcd_pad(nfin)) return;
-    const int64_t nw = 2 * (gtile_end - gtile0);  // tile edges
-    const int64_t gw = xcd_item(blockIdx.x - xcd_pad(nfin), kWaves, wave, nw);
-    if (gw >= nw) return;
+    const int lane = threadIdx.x & 63;
     const int64_t gtile = gtile0 + (gw >> 1);
     const int edge = (int)(gw & 1);
     int64_t lt;
@@ -1011,21 +1100,59 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
         b = (uint32_t)(nt * NB) + bsl[nt * NB + pn];
     }
     const uint64_t m = gmem(R.cross)[2 * lt + edge];
-    const bool seam = (cut == 1 && edge == 0 && T.tx == T.ntx - 1) || (cut == 2 && edge == 1 && T.ty == T.nty - 1);
+    const bool seam =
+        CUT && ((cut == 1 && edge == 0 && T.tx == T.ntx - 1) || (cut == 2 && edge == 1 && T.ty == T.nty - 1));
     const bool on = !seam && lane < nlinks && ((m >> lane) & 1ull);
-    // one union per distinct pair of the wave: the lowest lane holding a pair
-    // not seen yet leads it, and every lane with the same pair drops out
-    uint64_t todo = __ballot(on && a != b);
+    // dedup 0: one union per distinct pair of the wave (the lowest lane
+    // holding a pair not seen yet leads it, and every lane with the same pair
+    // drops out); dedup 1: a lane drops out only when the lane before it holds
+    // the same pair (a tuning choice: the partition, and so every root and
+    // coin, is the same either way)
     bool lead = false;
-    while (todo) {
-        const int l = __ffsll((long long)todo) - 1;
-        const uint32_t la = __shfl(a, l), lb = __shfl(b, l);
-        lead = lead || lane == l;
-        todo &= ~__ballot(on && a == la && b == lb);
+    if constexpr (DEDUP == 0) {
+        uint64_t todo = __ballot(on && a != b);
+        while (todo) {
+            const int l = __ffsll((long long)todo) - 1;
+            const uint32_t la = __shfl(a, l), lb = __shfl(b, l);
+            lead = lead || lane == l;
+            todo &= ~__ballot(on && a == la && b == lb);
+        }
+    } else {
+        const uint32_t pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
+        const bool prev_on = lane > 0 && ((m >> (lane - 1)) & 1ull) && lane - 1 < nlinks;
+        lead = on && a != b && !(prev_on && pa == a && pb == b);
     }
-    if (lead) union_nodes(gmem(cut == 0 ? R.node : R.node_cut[cut - 1]), a, b);
+    if (lead) union_nodes(gmem(CUT ? R.node_cut[cut - 1] : R.node), a, b);
     // mirror direction of the sweep after the one labelled last
     if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, R.st->tl + 1);
+}
+
+// epw (edges per wave, 1 or 2; a tuning choice): a wave unites epw
+// consecutive edges of its XCD's band one after the other, and the grid has
+// that many times fewer waves.
+// DEDUP and EPW: the merge schedule (pair deduplication, tile edges per
+// wave); CUT: a forest copy of the wrapping check (cut 1 or 2)
+template <int DEDUP, int EPW, bool CUT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge(
+    const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, const uint32_t *__restrict__ fin_rep,
+    int32_t nrep, int64_t gtile0, int64_t gtile_end, int32_t next_dir, int64_t nfin, int32_t cut)
+{
+    // the first nfin blocks: deferred finalisation, stage 1 (chunk c of
+    // replica r; first in the grid, so that they overlap the unions)
+    if (blockIdx.x < nfin) {
+        __shared__ double red[kWaves * kNumSums];
+        fin_chunk(reps, fin_rep, nrep, blockIdx.x, red);
+        return;
+    }
+    const int wave = threadIdx.x >> 6;
+    if (blockIdx.x < xcd_pad(nfin)) return;
+    const int64_t nw = 2 * (gtile_end - gtile0);  // tile edges
+#pragma unroll
+    for (int q = 0; q < EPW; ++q) {
+        const int64_t gw = xcd_item(blockIdx.x - xcd_pad(nfin), kWaves * EPW, wave * EPW + q, nw);
+        if (gw >= nw) return;
+        merge_edge<DEDUP, CUT>(reps, tile_rep, nrep, gtile0, gw, next_dir, cut);
+    }
 }
 
 // ------------------------------------------------- coins of edge positions
@@ -1036,7 +1163,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
 // boundary label's slot is itself an edge position).  One wave per tile: lane
 // l holds positions l, l + 64, l + 128, l + 192 (NB <= 256), walks their
 // paths to the roots together, and the coins are exchanged by ballots.
-__global__ __launch_bounds__(kThreads) void k_resolve(const RepDesc *__restrict__ reps,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_resolve(const RepDesc *__restrict__ reps,
                                                        const uint32_t *__restrict__ tile_rep, int32_t nrep,
                                                        int64_t gtile0, int64_t gtile_end, int64_t nfin, FlipArgs fa)
 {
@@ -1514,7 +1641,7 @@ size_t lds_bytes_tile(int TH)
     // and the column sums of the waves (8 waves for 64-row tiles, else 4)
     const size_t spins = (size_t)(TH + 1) * 65 * sizeof(float2);
     const size_t later = (size_t)64 * TH * sizeof(uint32_t) + (size_t)(TH >= 64 ? 8 : 4) * 64 * 2 * sizeof(double);
-    return std::max(spins, later) + (size_t)(3 * TH + 4) * sizeof(uint64_t);
+    return std::max(spins, later) + (size_t)(5 * TH + 4) * sizeof(uint64_t);
 }
 
 // Element-wise kernels over N sites loop with a grid stride: a dispatch holds
@@ -1548,41 +1675,46 @@ hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s)
 }
 
 template <int MODE, int BT, int NW>
-static void tile_dispatch_bt(const Launch &lc, hipStream_t s)
+static void tile_dispatch_bt(const Launch &lc, const FlipArgs &fa, hipStream_t s)
 {
     const size_t lds = lds_bytes_tile(lc.max_th);
     const dim3 grid((unsigned)xcd_blocks(lc.gtile_end - lc.gtile0, 1)), block(NW * 64);
     if (lc.big_index)
         hipLaunchKernelGGL((k_tile<uint64_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
-                           lc.gtile0, lc.gtile_end);
+                           lc.gtile0, lc.gtile_end, fa);
     else
         hipLaunchKernelGGL((k_tile<uint32_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
-                           lc.gtile0, lc.gtile_end);
+                           lc.gtile0, lc.gtile_end, fa);
 }
 
 // Fixed-size tiles of 64 columns when every replica of the launch has that
 // shape: 8 rows per wave, 4 waves (32 rows) or 8 waves (64 rows), or 4 rows per
 // wave for 16-row tiles; the general path (4 waves) otherwise.
 template <int MODE>
-static void tile_dispatch(const Launch &lc, hipStream_t s)
+static void tile_dispatch(const Launch &lc, const FlipArgs &fa, hipStream_t s)
 {
     if (MODE != M_PLANES && lc.uniform_th == 64 && lc.uniform_tw == 64)
-        tile_dispatch_bt<MODE, 8, 8>(lc, s);
+        tile_dispatch_bt<MODE, 8, 8>(lc, fa, s);
     else if (MODE != M_PLANES && lc.uniform_th == 32 && lc.uniform_tw == 64)
-        tile_dispatch_bt<MODE, 8, 4>(lc, s);
+        tile_dispatch_bt<MODE, 8, 4>(lc, fa, s);
     else if (MODE != M_PLANES && lc.uniform_th == 16 && lc.uniform_tw == 64)
-        tile_dispatch_bt<MODE, 4, 4>(lc, s);
+        tile_dispatch_bt<MODE, 4, 4>(lc, fa, s);
     else
-        tile_dispatch_bt<MODE, 0, 4>(lc, s);
+        tile_dispatch_bt<MODE, 0, 4>(lc, fa, s);
 }
 
-hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
+hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s, const FlipArgs *fa)
 {
+    FlipArgs f;
+    if (fa) f = *fa;
+    else std::memset(&f, 0, sizeof f);
     switch (mode) {
-    case TILE_BONDS: tile_dispatch<M_BONDS>(lc, s); break;
-    case TILE_FLIP: tile_dispatch<M_FLIP>(lc, s); break;
-    case TILE_FUSED: tile_dispatch<M_FUSED>(lc, s); break;
-    case TILE_PLANES: tile_dispatch<M_PLANES>(lc, s); break;
+    case TILE_BONDS: tile_dispatch<M_BONDS>(lc, f, s); break;
+    case TILE_FLIP: tile_dispatch<M_FLIP>(lc, f, s); break;
+    case TILE_FUSED: tile_dispatch<M_FUSED>(lc, f, s); break;
+    case TILE_PLANES: tile_dispatch<M_PLANES>(lc, f, s); break;
+    case TILE_SPEC: tile_dispatch<M_SPEC>(lc, f, s); break;
+    case TILE_PLSEL: tile_dispatch<M_PLSEL>(lc, f, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1590,11 +1722,21 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s)
 
 hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s)
 {
-    const int64_t nblk = xcd_blocks(2 * (lc.gtile_end - lc.gtile0), kWaves);  // one wave per tile edge
+    const int epw = lc.merge_epw == 2 ? 2 : 1;
+    const int64_t nblk = xcd_blocks(2 * (lc.gtile_end - lc.gtile0), kWaves * epw);  // epw tile edges per wave
     const int64_t nfin = fin ? lc.nfin : 0;
     const dim3 grid((unsigned)(xcd_pad(nfin) + nblk)), block(kThreads);
-    hipLaunchKernelGGL(k_merge, grid, block, 0, s, lc.reps, lc.tile_rep, lc.fin_rep, lc.nrep, lc.gtile0,
-                       lc.gtile_end, (int32_t)next_dir, nfin, 0);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, 0, s, lc.reps, lc.tile_rep, lc.fin_rep, lc.nrep, lc.gtile0,
+                           lc.gtile_end, (int32_t)next_dir, nfin, (int32_t)0);
+    };
+    if (lc.dedup == 0) {
+        if (epw == 1) go(k_merge<0, 1, false>);
+        else go(k_merge<0, 2, false>);
+    } else {
+        if (epw == 1) go(k_merge<1, 1, false>);
+        else go(k_merge<1, 2, false>);
+    }
     return hipGetLastError();
 }
 
@@ -1602,8 +1744,12 @@ hipError_t launch_merge_cut(const Launch &lc, int cut, hipStream_t s)
 {
     if (cut != 1 && cut != 2) return hipErrorInvalidValue;
     const int64_t nblk = xcd_blocks(2 * (lc.gtile_end - lc.gtile0), kWaves);
-    hipLaunchKernelGGL(k_merge, dim3((unsigned)nblk), dim3(kThreads), 0, s, lc.reps, lc.tile_rep, lc.fin_rep,
-                       lc.nrep, lc.gtile0, lc.gtile_end, 0, (int64_t)0, (int32_t)cut);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kThreads), 0, s, lc.reps, lc.tile_rep, lc.fin_rep,
+                           lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)0, (int64_t)0, (int32_t)cut);
+    };
+    if (lc.dedup == 0) go(k_merge<0, 1, true>);
+    else go(k_merge<1, 1, true>);
     return hipGetLastError();
 }
 

@@ -22,10 +22,14 @@ struct Launch {
     int64_t gtile0, gtile_end;
     const uint32_t *fin_rep;  // device: replica of every finalisation chunk (unused if nrep == 1)
     int64_t nfin;             // finalisation chunks of all replicas
+    int32_t dedup = 0;        // merge: 0 one union per distinct node pair of a wave, 1 per run of equal neighbours
+    int32_t merge_epw = 1;    // merge: tile edges per wave (1 or 2)
 };
 
-// Modes of the tile kernel.
-enum { TILE_BONDS = 0, TILE_FLIP = 1, TILE_FUSED = 2, TILE_PLANES = 3 };
+// Modes of the tile kernel.  TILE_SPEC: flip of sweep t and the links of
+// sweep t+1 for both betas a PCC step after sweep t may choose (no labels);
+// TILE_PLSEL: labels of a sweep from the links of the beta that was chosen.
+enum { TILE_BONDS = 0, TILE_FLIP = 1, TILE_FUSED = 2, TILE_PLANES = 3, TILE_SPEC = 4, TILE_PLSEL = 5 };
 
 // Per-launch arguments of the flip kernel's finalisation (observables, PCC).
 struct FlipArgs {
@@ -45,7 +49,8 @@ hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_
 hipError_t launch_edge_refresh(const RepDesc *d_reps, int32_t r, int64_t ntiles, hipStream_t s);
 hipError_t launch_init_fourier(const RepDesc *d_reps, int32_t r, int64_t L, hipStream_t s);
 hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s);
-hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s);
+// fa: the sweep's finalisation arguments (TILE_SPEC reads its PCC rule), or null.
+hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s, const FlipArgs *fa = nullptr);
 // Union across tile edges; next_dir: also draw the next sweep's direction.
 // fin: also the first stage of the deferred finalisation of the previous,
 // fused sweep (the second runs with the edge coins, given its arguments).

@@ -1,4 +1,4 @@
-"""Tile-height autotuner (paper_1210_6116_amd.autotune).
+"""Autotuner (paper_1210_6116_amd.autotune): tile height and merge schedule.
 
 The tuner times each candidate tile height on the replica set and keeps the
 fastest; the choice only changes speed, never results: links, labels and coins
@@ -52,3 +52,44 @@ def test_results_do_not_depend_on_tile_height():
         for k in range(len(specs)):
             assert np.array_equal(states[k][0], ref_states[k][0]), (rows, k)
             assert np.array_equal(states[k][1], ref_states[k][1]), (rows, k)
+
+
+def test_merge_schedule_pick_and_cache(tmp_path, monkeypatch):
+    """One L = 2048 lattice: every merge schedule is timed, the pick is the
+    fastest, and the cache returns it."""
+    from paper_1210_6116_amd import autotune
+    monkeypatch.setenv("XDG_CACHE_HOME", str(tmp_path))
+    specs = [dict(L=2048, beta=1.12, seed=0xB0B)]
+    best, timings = autotune.tune_merge(specs, 32, sweeps=8, warmup=2, use_cache=False)
+    print("merge schedule:", best, {k: "%.1f us" % (v * 1e6) for k, v in timings.items()}, flush=True)
+    assert set(timings) == set(autotune.merge_candidates())
+    assert timings[best] == min(timings.values())
+    again, cached = autotune.tune_merge(specs, 32, use_cache=True)
+    assert again == best and cached == pytest.approx(timings)
+
+
+@pytest.mark.parametrize("beta", [0.5, 1.12])
+def test_results_do_not_depend_on_merge_schedule(beta):
+    """Every (dedup, edges per wave) choice: bit-identical traces, spins and
+    labels, for a replica batch (graph replay included) and one lattice."""
+    import paper_1210_6116_amd as xy
+    from paper_1210_6116_amd import autotune
+    specs = [dict(L=1024, beta=beta, seed=0xD0D)] + [dict(L=L, beta=beta, seed=0xD0E + k, rep=k)
+                                                    for k, L in enumerate((64, 256, 128))]
+    runs = {}
+    for choice in autotune.merge_candidates():
+        lat = xy.Lattices(specs)
+        autotune.configure(lat, choice)
+        tr = lat.sweep(7, trace=True)
+        lat.sweep_graph(3, 2)
+        tr2 = lat.sweep(1, trace=True)
+        runs[choice] = (tr, tr2, [lat.get_state(k) for k in range(len(specs))],
+                        [lat.labels(k) for k in range(len(specs))])
+        lat.close()
+    ref = runs[autotune.merge_candidates()[0]]
+    for choice, (tr, tr2, st, lab) in runs.items():
+        for f in ("E", "m2", "ex", "sx", "ey", "sy", "ups_x", "mk2", "near_ties"):
+            assert np.array_equal(tr[f], ref[0][f]) and np.array_equal(tr2[f], ref[1][f]), (choice, f)
+        for k in range(len(specs)):
+            assert np.array_equal(st[k][0], ref[2][k][0]) and np.array_equal(st[k][1], ref[2][k][1]), (choice, k)
+            assert np.array_equal(lab[k], ref[3][k]), (choice, k)
