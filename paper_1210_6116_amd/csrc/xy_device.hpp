@@ -107,9 +107,19 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        // three-input exclusive or in one instruction (truth table 0x96)
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
-        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+        uint32_t n0, n2;
+        if (round < 2) {
+            // the first two rounds: where the counter's upper words are the
+            // same in every lane (as in the sweep's draws) half of these
+            // products and exclusive ors are scalar; grouping the key with
+            // them keeps them so
+            n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
+            n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+        } else {
+            // three-input exclusive or in one instruction (truth table 0x96)
+            n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+            n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+        }
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

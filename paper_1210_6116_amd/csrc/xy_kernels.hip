@@ -168,10 +168,11 @@ __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v)
 // v_cndmask with m as its lane mask.
 __device__ __forceinline__ uint32_t lane_select(uint64_t m, uint32_t a, uint32_t b)
 {
-    uint32_t r;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(m));
-    return r;
+    return __builtin_amdgcn_inverse_ballot_w64(m) ? a : b;
 }
+// Bit `lane` of the wave-uniform mask m, as a lane predicate (m itself serves
+// as the mask of a branch or a select: no vector instruction)
+__device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
 // ------------------------------------------------------- union-find in LDS
 __device__ __forceinline__ uint32_t lds_load(const uint32_t *p)
@@ -478,6 +479,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     // the sweep counter, so these loads overlap its read
     float c0[BMAX], s0[BMAX];
     uint32_t lv[BMAX];  // labels of the flipped sweep (flip modes)
+
     if constexpr (!FROM_PLANES) {
 #pragma unroll
         for (int k = 0; k < B; ++k) {
@@ -520,23 +522,23 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     if constexpr (FLIP) {
         const XY_G float2 *__restrict__ eg = gmem(R.edge[par]);
         const double rx = cload(&R.st->dir[par][0]), ry = cload(&R.st->dir[par][1]);
+        // (2 a) r = a (2 r) exactly: doubling is exact in binary floating point
+        const double rx2 = 2.0 * rx, ry2 = 2.0 * ry;
         const bool renorm = ((t + 1) % kRenormEvery) == 0;
         const uint32_t tf = (uint32_t)t;
-        auto flip_one = [&](bool f, float c0, float s0, float &c1, float &s1) {
-            c1 = c0;
-            s1 = s0;
+        auto reflect = [&](bool f, float &c1, float &s1) {
             if (f) {
-                const double c = c0, s = s0;
-                const double g = 2.0 * (c * rx + s * ry);
-                c1 = (float)(c - g * rx);
-                s1 = (float)(s - g * ry);
-            }
-            if (renorm) {
                 const double c = c1, s = s1;
-                const double n = sqrt(c * c + s * s);
-                c1 = (float)(c / n);
-                s1 = (float)(s / n);
+                const double a = c * rx + s * ry;
+                c1 = (float)(c - a * rx2);
+                s1 = (float)(s - a * ry2);
             }
+        };
+        auto renormalise = [&](float &c1, float &s1) {
+            const double c = c1, s = s1;
+            const double n = sqrt(c * c + s * s);
+            c1 = (float)(c / n);
+            s1 = (float)(s / n);
         };
         // halo: right column and bottom row of the neighbouring tiles (spins
         // before the sweep from their edge copies, coins from their edge-position
@@ -575,35 +577,49 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
             rcoin[y] = two >> ((uint32_t)site0 & 31u);
         }
         if (hslot >= 0) {
-            float c1, s1;
-            flip_one(hcoin, he.x, he.y, c1, s1);
+            float c1 = he.x, s1 = he.y;
+            reflect(hcoin, c1, s1);
+            if (renorm) renormalise(c1, s1);
             spin[hslot] = make_float2(c1, s1);
         }
         __syncthreads();
+        // the wave's sites: reflections, then (every kRenormEvery sweeps, the
+        // same in every lane) the renormalisation, then the stores; the
+        // spins of the sweep are updated in place
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             if (own(k)) {
-                const IT i = T.site(yb + k, lane);
                 const uint32_t l = lv[k];
                 bool f;
                 if constexpr (FIXED) {
-                    f = (((const uint32_t *)rcoin)[l >> 5] >> (l & 31u)) & 1u;
+                    // (the bit field extract takes its offset modulo 32)
+                    f = __builtin_amdgcn_ubfe(((const uint32_t *)rcoin)[l >> 5], l, 1u) != 0u;
                 } else {
                     const uint32_t nsite = (uint32_t)(TW * TH), q = l - nsite;
                     f = l >= nsite ? ((scoin[q >> 6] >> (q & 63u)) & 1ull)
                                    : ((rcoin[l >> T.log2TW] >> (l & (uint32_t)(TW - 1))) & 1ull);
                 }
-                float c1, s1;
+                reflect(f, c0[k], s0[k]);
+            }
+        }
+        if (renorm) {
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (own(k)) renormalise(c0[k], s0[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (own(k)) {
+                const float c1 = c0[k], s1 = s0[k];
                 // every site is stored, flipped or not: lines written in
                 // part (cluster edges) cost the memory more than whole lines
-                flip_one(f, c0[k], s0[k], c1, s1);
                 if constexpr (WIDE) {
                     // streaming stores (2^32-site lattices)
                     __builtin_nontemporal_store(c1, &gel(cpw, woff(k, lane)));
                     __builtin_nontemporal_store(s1, &gel(spw, woff(k, lane)));
                 } else {
-                    gel(cp, i) = c1;
-                    gel(sp, i) = s1;
+                    gel(cp, T.site(yb + k, lane)) = c1;
+                    gel(sp, T.site(yb + k, lane)) = s1;
                 }
                 spin[(yb + k) * SS + lane] = make_float2(c1, s1);
             }
@@ -958,10 +974,12 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
         if (k > 0) {
             // a lane whose label above differs from its run's records their
             // union, unless its left neighbour in the run offers the same label
+            // (lane 0 has no left neighbour: bit 0 of xm << 1 is clear, so its
+            // cleft, zero, is never looked at)
             const uint32_t cleft =
-                (uint32_t)__builtin_amdgcn_update_dpp((int)NONE, (int)c2, 0x138, 0xf, 0xf, false);  // wave_shr:1
+                (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c2, 0x138, 0xf, 0xf, true);  // wave_shr:1
             const uint64_t need = up & __ballot(c2 != lab) & ~((xm << 1) & __ballot(cleft == c2));
-            if (lane_select(need, 1u, 0u)) union_lds(lab_s, c2, lab);
+            if (lane_bit(need)) union_lds(lab_s, c2, lab);
         }
         lprev = lab;
     }
@@ -975,7 +993,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
             const uint64_t vv = bym[y] & twmask;
             const uint64_t h0 = bxm[y] & inner, h1 = bxm[y + 1] & inner;
             const uint64_t need = vv & ~(vv & (vv << 1) & (h0 << 1) & (h1 << 1));
-            if ((need >> lane) & 1ull)
+            if (lane_bit(need))
                 union_lds(lab_s, (uint32_t)(y * TW + lane), (uint32_t)((y + 1) * TW + lane));
         }
     }
