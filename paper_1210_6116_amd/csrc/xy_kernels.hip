@@ -949,6 +949,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     //    their union; a run touching none is labelled by its first site.
     //    Labels are sites of this band only, so the waves do not interact.
     uint32_t lprev = NONE;
+    uint32_t pend = 0u;  // bit k: a union of row k is left to the loop after the scan
 #pragma unroll
     for (int k = 0; k < B; ++k) {
         const int y = yb + k;
@@ -979,9 +980,19 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
             const uint32_t cleft =
                 (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c2, 0x138, 0xf, 0xf, true);  // wave_shr:1
             const uint64_t need = up & __ballot(c2 != lab) & ~((xm << 1) & __ballot(cleft == c2));
-            if (lane_bit(need)) union_lds(lab_s, c2, lab);
+            pend = lane_bit(need) ? pend | (1u << k) : pend;
         }
         lprev = lab;
+    }
+    // the unions the scan recorded, all rows in one loop: the site above and
+    // the site itself stand for the two labels (every site's entry holds its
+    // label, and the unions only ever point an entry at another member of
+    // its set)
+    while (pend) {
+        const int k = __builtin_ctz(pend);
+        pend &= pend - 1u;
+        const uint32_t q = (uint32_t)((yb + k) * TW + lane);
+        union_lds(lab_s, q - (uint32_t)TW, q);
     }
     __syncthreads();
     if constexpr (FLIP) fold_site_sums();
