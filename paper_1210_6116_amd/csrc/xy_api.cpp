@@ -912,8 +912,8 @@ int xy_set_merge(xy_handle *h, int32_t dedup, int32_t edges_per_wave)
     if (rc) return rc;
     if (dedup != XY_DEDUP_WAVE && dedup != XY_DEDUP_NEIGHBOUR)
         return fail(XY_EINVAL, "merge deduplication policy %d unknown", dedup);
-    if (edges_per_wave != 1 && edges_per_wave != 2)
-        return fail(XY_EINVAL, "edges_per_wave=%d is not 1 or 2", edges_per_wave);
+    if (edges_per_wave != 1 && edges_per_wave != 2 && edges_per_wave != 4)
+        return fail(XY_EINVAL, "edges_per_wave=%d is not 1, 2 or 4", edges_per_wave);
     h->dedup = dedup;
     h->merge_epw = edges_per_wave;
     return XY_OK;

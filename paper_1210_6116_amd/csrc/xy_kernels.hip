@@ -164,6 +164,39 @@ __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v)
     return v;
 }
 
+// v plus the v of lane ^ OFF (a butterfly step of a wave reduction): the
+// exchange by ds_swizzle inside each half of the wave (bit-mask mode: xor
+// OFF) or by ds_bpermute across the halves, so no step spends vector
+// instructions on lane indices.  The same pairs as __shfl_xor, so the same
+// sums bit for bit.
+template <int OFF>
+__device__ __forceinline__ double xor_add(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int lo2, hi2;
+    if constexpr (OFF == 32) {
+        const int addr = (int)((threadIdx.x & 63) ^ 32) << 2;
+        lo2 = __builtin_amdgcn_ds_bpermute(addr, lo);
+        hi2 = __builtin_amdgcn_ds_bpermute(addr, hi);
+    } else {
+        constexpr int pat = (OFF << 10) | 0x1F;  // and 0x1F, or 0, xor OFF
+        lo2 = __builtin_amdgcn_ds_swizzle(lo, pat);
+        hi2 = __builtin_amdgcn_ds_swizzle(hi, pat);
+    }
+    return v + __hiloint2double(hi2, lo2);
+}
+
+// Sum of v over the 64 lanes of the wave, in every lane.
+__device__ __forceinline__ double wave_total(double v)
+{
+    v = xor_add<32>(v);
+    v = xor_add<16>(v);
+    v = xor_add<8>(v);
+    v = xor_add<4>(v);
+    v = xor_add<2>(v);
+    return xor_add<1>(v);
+}
+
 // Bit `lane` of the wave-uniform mask m selects a (set) or b, as one
 // v_cndmask with m as its lane mask.
 __device__ __forceinline__ uint32_t lane_select(uint64_t m, uint32_t a, uint32_t b)
@@ -305,10 +338,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *red /* NW*K */
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    }
+    for (int k = 0; k < K; ++k) v[k] = wave_total(v[k]);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
@@ -332,10 +362,7 @@ __device__ __forceinline__ void wave_sums(double (&v)[K], double *red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    }
+    for (int k = 0; k < K; ++k) v[k] = wave_total(v[k]);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
@@ -812,10 +839,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                 f[5] = f[1] * sk;
             }
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) f[k] += __shfl_xor(f[k], off);
-            }
+            for (int k = 0; k < 6; ++k) f[k] = wave_total(f[k]);
             if (lane == 0) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) gmem(R.partials)[(kPairSums + k) * R.ntiles + lt] = f[k];
@@ -969,7 +993,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
         const uint32_t run_id = __builtin_amdgcn_mbcnt_hi((uint32_t)(ends >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)ends, 0u));
         const uint32_t key = (run_id << 16) | (0xFFFFu - c2);
-        const uint32_t pm = __shfl(wave_prefix_max(key), (int)end);
+        const uint32_t pm = (uint32_t)__builtin_amdgcn_ds_bpermute((int)end << 2, (int)wave_prefix_max(key));
         const uint32_t lab = 0xFFFFu - (pm & 0xFFFFu);
         if (act) lab_s[y * TW + lane] = lab;
         if (k > 0) {
@@ -1107,9 +1131,20 @@ __device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa
 // lattice's seam along x (right edges of the last tile column) / along y
 // (bottom edges of the last tile row).
 // The unions of tile edge gw (2 x tile + 0: right edge, + 1: bottom edge).
-template <int DEDUP, bool CUT>
-__device__ __forceinline__ void merge_edge(const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep,
-                                           int32_t nrep, int64_t gtile0, int64_t gw, int32_t next_dir, int32_t cut)
+// One tile edge of the merge: the lane's link over it (the node pair its two
+// end components are slots of) and the node array the unions go to.
+struct EdgeLinks {
+    uint32_t a, b;                  // boundary nodes of the link's two ends
+    uint64_t m;                     // the edge's active links (bit = lane)
+    bool on;                        // the lane's link is active and not cut
+    int nlinks;                     // links over the edge
+    XY_G unsigned long long *P;     // forest the unions go to
+};
+
+template <bool CUT>
+__device__ __forceinline__ EdgeLinks edge_links(const RepDesc *__restrict__ reps,
+                                                const uint32_t *__restrict__ tile_rep, int32_t nrep, int64_t gtile0,
+                                                int64_t gw, int32_t next_dir, int32_t cut)
 {
     const int lane = threadIdx.x & 63;
     const int64_t gtile = gtile0 + (gw >> 1);
@@ -1118,47 +1153,54 @@ __device__ __forceinline__ void merge_edge(const RepDesc *__restrict__ reps, con
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
     const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
     const int NB = R.nb;
-    const int nlinks = edge ? T.TW : T.TH;
-    uint32_t a = 0, b = 0;
-    if (lane < nlinks) {  // read with the link mask, not after it
+    EdgeLinks e;
+    e.nlinks = edge ? T.TW : T.TH;
+    e.a = 0;
+    e.b = 0;
+    if (lane < e.nlinks) {  // read with the link mask, not after it
         const XY_G uint8_t *bsl = gmem(R.bslot);
         const int64_t nt = edge ? T.down_tile() : T.right_tile();
         const int pa = edge ? T.TW + lane : 2 * T.TW + T.TH + lane;  // own bottom row / right column
         const int pn = edge ? lane : 2 * T.TW + lane;                 // neighbour's top row / left column
-        a = (uint32_t)(lt * NB) + bsl[lt * NB + pa];
-        b = (uint32_t)(nt * NB) + bsl[nt * NB + pn];
+        e.a = (uint32_t)(lt * NB) + bsl[lt * NB + pa];
+        e.b = (uint32_t)(nt * NB) + bsl[nt * NB + pn];
     }
-    const uint64_t m = gmem(R.cross)[2 * lt + edge];
+    e.m = gmem(R.cross)[2 * lt + edge];
     const bool seam =
         CUT && ((cut == 1 && edge == 0 && T.tx == T.ntx - 1) || (cut == 2 && edge == 1 && T.ty == T.nty - 1));
-    const bool on = !seam && lane < nlinks && ((m >> lane) & 1ull);
-    // dedup 0: one union per distinct pair of the wave (the lowest lane
-    // holding a pair not seen yet leads it, and every lane with the same pair
-    // drops out); dedup 1: a lane drops out only when the lane before it holds
-    // the same pair (a tuning choice: the partition, and so every root and
-    // coin, is the same either way)
-    bool lead = false;
-    if constexpr (DEDUP == 0) {
-        uint64_t todo = __ballot(on && a != b);
-        while (todo) {
-            const int l = __ffsll((long long)todo) - 1;
-            const uint32_t la = __shfl(a, l), lb = __shfl(b, l);
-            lead = lead || lane == l;
-            todo &= ~__ballot(on && a == la && b == lb);
-        }
-    } else {
-        const uint32_t pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
-        const bool prev_on = lane > 0 && ((m >> (lane - 1)) & 1ull) && lane - 1 < nlinks;
-        lead = on && a != b && !(prev_on && pa == a && pb == b);
-    }
-    if (lead) union_nodes(gmem(CUT ? R.node_cut[cut - 1] : R.node), a, b);
+    e.on = !seam && lane < e.nlinks && ((e.m >> lane) & 1ull);
+    e.P = gmem(CUT ? R.node_cut[cut - 1] : R.node);
     // mirror direction of the sweep after the one labelled last
     if (next_dir && lt == 0 && edge == 0 && lane == 0) compute_direction(R, R.st->tl + 1);
+    return e;
 }
 
-// epw (edges per wave, 1 or 2; a tuning choice): a wave unites epw
-// consecutive edges of its XCD's band one after the other, and the grid has
-// that many times fewer waves.
+// Does the lane lead the union of its pair?  dedup 0: one union per distinct
+// pair of the edge (the lowest lane holding a pair not seen yet leads it, and
+// every lane with the same pair drops out); dedup 1: a lane drops out only
+// when the lane before it holds the same pair (a tuning choice: the
+// partition, and so every root and coin, is the same either way).
+template <int DEDUP>
+__device__ __forceinline__ bool leads(const EdgeLinks &e)
+{
+    const int lane = threadIdx.x & 63;
+    bool lead = false;
+    if constexpr (DEDUP == 0) {
+        uint64_t todo = __ballot(e.on && e.a != e.b);
+        while (todo) {
+            const int l = __ffsll((long long)todo) - 1;
+            const uint32_t la = __shfl(e.a, l), lb = __shfl(e.b, l);
+            lead = lead || lane == l;
+            todo &= ~__ballot(e.on && e.a == la && e.b == lb);
+        }
+    } else {
+        const uint32_t pa = __shfl_up(e.a, 1), pb = __shfl_up(e.b, 1);
+        const bool prev_on = lane > 0 && ((e.m >> (lane - 1)) & 1ull) && lane - 1 < e.nlinks;
+        lead = e.on && e.a != e.b && !(prev_on && pa == e.a && pb == e.b);
+    }
+    return lead;
+}
+
 // DEDUP and EPW: the merge schedule (pair deduplication, tile edges per
 // wave); CUT: a forest copy of the wrapping check (cut 1 or 2)
 template <int DEDUP, int EPW, bool CUT>
@@ -1173,14 +1215,56 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
         fin_chunk(reps, fin_rep, nrep, blockIdx.x, red);
         return;
     }
-    const int wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (blockIdx.x < xcd_pad(nfin)) return;
     const int64_t nw = 2 * (gtile_end - gtile0);  // tile edges
-#pragma unroll
-    for (int q = 0; q < EPW; ++q) {
-        const int64_t gw = xcd_item(blockIdx.x - xcd_pad(nfin), kWaves * EPW, wave * EPW + q, nw);
+    if constexpr (EPW == 1) {
+        const int64_t gw = xcd_item(blockIdx.x - xcd_pad(nfin), kWaves, wave, nw);
         if (gw >= nw) return;
-        merge_edge<DEDUP, CUT>(reps, tile_rep, nrep, gtile0, gw, next_dir, cut);
+        const EdgeLinks e = edge_links<CUT>(reps, tile_rep, nrep, gtile0, gw, next_dir, cut);
+        if (leads<DEDUP>(e)) union_nodes(e.P, e.a, e.b);
+    } else {
+        // EPW tile edges per wave: their links read together, then the
+        // leading pairs of all of them packed into the wave's lanes (through
+        // its part of LDS), so that their unions run side by side rather
+        // than one edge after the other
+        __shared__ uint2 pair_s[kWaves][EPW * 64];
+        __shared__ uint8_t edge_s[kWaves][EPW * 64];
+        EdgeLinks e[EPW];
+        int ne = 0;  // edges of this wave (the same in every lane)
+#pragma unroll
+        for (int q = 0; q < EPW; ++q) {
+            const int64_t gw = xcd_item(blockIdx.x - xcd_pad(nfin), kWaves * EPW, wave * EPW + q, nw);
+            if (gw >= nw) break;
+            e[q] = edge_links<CUT>(reps, tile_rep, nrep, gtile0, gw, next_dir, cut);
+            ne = q + 1;
+        }
+        uint32_t n = 0;  // pairs packed (the same in every lane)
+#pragma unroll
+        for (int q = 0; q < EPW; ++q) {
+            if (q >= ne) break;
+            const bool lead = leads<DEDUP>(e[q]);
+            const uint64_t bm = __ballot(lead);
+            if (lead) {
+                const uint32_t r =
+                    n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+                pair_s[wave][r] = make_uint2(e[q].a, e[q].b);
+                edge_s[wave][r] = (uint8_t)q;
+            }
+            n += (uint32_t)__popcll(bm);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t j = (uint32_t)lane; j < n; j += 64) {
+            const uint2 pr = pair_s[wave][j];
+            const int q = edge_s[wave][j];
+            XY_G unsigned long long *P = e[0].P;
+#pragma unroll
+            for (int q2 = 1; q2 < EPW; ++q2)
+                if (q == q2) P = e[q2].P;
+            union_nodes(P, pr.x, pr.y);
+        }
     }
 }
 
@@ -1751,7 +1835,7 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s, const FlipArgs
 
 hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s)
 {
-    const int epw = lc.merge_epw == 2 ? 2 : 1;
+    const int epw = lc.merge_epw == 4 ? 4 : lc.merge_epw == 2 ? 2 : 1;
     const int64_t nblk = xcd_blocks(2 * (lc.gtile_end - lc.gtile0), kWaves * epw);  // epw tile edges per wave
     const int64_t nfin = fin ? lc.nfin : 0;
     const dim3 grid((unsigned)(xcd_pad(nfin) + nblk)), block(kThreads);
@@ -1761,10 +1845,12 @@ hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s
     };
     if (lc.dedup == 0) {
         if (epw == 1) go(k_merge<0, 1, false>);
-        else go(k_merge<0, 2, false>);
+        else if (epw == 2) go(k_merge<0, 2, false>);
+        else go(k_merge<0, 4, false>);
     } else {
         if (epw == 1) go(k_merge<1, 1, false>);
-        else go(k_merge<1, 2, false>);
+        else if (epw == 2) go(k_merge<1, 2, false>);
+        else go(k_merge<1, 4, false>);
     }
     return hipGetLastError();
 }
