@@ -164,13 +164,11 @@ __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v)
     return v;
 }
 
-// v plus the v of lane ^ OFF (a butterfly step of a wave reduction): the
-// exchange by ds_swizzle inside each half of the wave (bit-mask mode: xor
-// OFF) or by ds_bpermute across the halves, so no step spends vector
-// instructions on lane indices.  The same pairs as __shfl_xor, so the same
-// sums bit for bit.
+// The v of lane ^ OFF: by ds_swizzle inside each half of the wave (bit-mask
+// mode: xor OFF) or by ds_bpermute across the halves, so no exchange spends
+// vector instructions on lane indices.
 template <int OFF>
-__device__ __forceinline__ double xor_add(double v)
+__device__ __forceinline__ double lane_xor(double v)
 {
     const int lo = __double2loint(v), hi = __double2hiint(v);
     int lo2, hi2;
@@ -183,7 +181,59 @@ __device__ __forceinline__ double xor_add(double v)
         lo2 = __builtin_amdgcn_ds_swizzle(lo, pat);
         hi2 = __builtin_amdgcn_ds_swizzle(hi, pat);
     }
-    return v + __hiloint2double(hi2, lo2);
+    return __hiloint2double(hi2, lo2);
+}
+
+// v plus the v of lane ^ OFF: a butterfly step (the same pairs as
+// __shfl_xor, so the same sums bit for bit).
+template <int OFF>
+__device__ __forceinline__ double xor_add(double v)
+{
+    return v + lane_xor<OFF>(v);
+}
+
+// One recursive-halving step over K values at lane distance D: the lane whose
+// bit D is clear keeps the first half (adding its partner's first half), the
+// other keeps the second half (stored first), so half as many values go
+// through the exchange as in a butterfly over all of them.
+template <int K, int D>
+__device__ __forceinline__ void halve(double (&w)[K])
+{
+    const bool upper = (threadIdx.x & D) != 0;
+#pragma unroll
+    for (int i = 0; i < K / 2; ++i) {
+        const double keep = upper ? w[i + K / 2] : w[i];
+        const double send = upper ? w[i] : w[i + K / 2];
+        w[i] = keep + lane_xor<D>(send);
+    }
+}
+
+// Sums over the 64 lanes of the wave of K values per lane (K = 4 or 8):
+// recursive halving over the top log2 K lane bits, then butterfly steps over
+// the rest.  On return lane l holds the sum of value l >> (6 - log2 K), so the
+// lanes l with l % (64 / K) == 0 hold one sum each.  A fixed order of
+// additions: the same sums in every run.
+template <int K>
+__device__ __forceinline__ double wave_sums_split(double (&w)[K])
+{
+    static_assert(K == 4 || K == 8, "K = 4 or 8");
+    double r;
+    if constexpr (K == 8) {
+        halve<8, 32>(w);
+        double u[4] = {w[0], w[1], w[2], w[3]};
+        halve<4, 16>(u);
+        double z[2] = {u[0], u[1]};
+        halve<2, 8>(z);
+        r = xor_add<4>(z[0]);
+    } else {
+        halve<4, 32>(w);
+        double z[2] = {w[0], w[1]};
+        halve<2, 16>(z);
+        r = xor_add<8>(z[0]);
+        r = xor_add<4>(r);
+    }
+    r = xor_add<2>(r);
+    return xor_add<1>(r);
 }
 
 // Sum of v over the 64 lanes of the wave, in every lane.
@@ -361,11 +411,18 @@ template <int K>
 __device__ __forceinline__ void wave_sums(double (&v)[K], double *red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if constexpr (K == 4 || K == 8) {
+        // (v is consumed)
+        const double r = wave_sums_split<K>(v);
+        constexpr int S = 64 / K;
+        if (lane % S == 0) red[wave * K + lane / S] = r;
+    } else {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_total(v[k]);
-    if (lane == 0) {
+        for (int k = 0; k < K; ++k) v[k] = wave_total(v[k]);
+        if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+            for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+        }
     }
 }
 
@@ -838,12 +895,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
                 f[4] = f[1] * ck;
                 f[5] = f[1] * sk;
             }
-#pragma unroll
-            for (int k = 0; k < 6; ++k) f[k] = wave_total(f[k]);
-            if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) gmem(R.partials)[(kPairSums + k) * R.ntiles + lt] = f[k];
-            }
+            double f8[8] = {f[0], f[1], f[2], f[3], f[4], f[5], 0.0, 0.0};
+            const double r = wave_sums_split<8>(f8);
+            if ((lane & 7) == 0 && lane < 48) gmem(R.partials)[(kPairSums + (lane >> 3)) * R.ntiles + lt] = r;
         }
     };
     // active-link bit planes of sweep tb from the row masks in LDS
