@@ -236,12 +236,15 @@ int xy_label_links_noalloc(int64_t L, int32_t label_bits, int32_t tile_rows, con
  * a wave of 64 such links often repeats a pair:
  *   XY_DEDUP_WAVE       (default) one union per distinct pair of the wave;
  *   XY_DEDUP_NEIGHBOUR  a link is skipped only when the link before it joins
- *                       the same pair (fewer ballots when pairs rarely repeat).
+ *                       the same pair (fewer ballots when pairs rarely repeat);
+ *   XY_DEDUP_HASH       one union per pair through a 64-entry table in LDS that
+ *                       the pairs hash to (a fixed cost per edge; a collision
+ *                       only repeats a union).
  * edges_per_wave: 1 (default), 2 or 4 tile edges per wave: their links are
  * read together and the pairs that lead a union packed into the wave's lanes,
  * so that the unions of all of them run side by side (half or a quarter as
  * many waves, each with more unions in flight).  XY_EINVAL for other values. */
-enum { XY_DEDUP_WAVE = 0, XY_DEDUP_NEIGHBOUR = 1 };
+enum { XY_DEDUP_WAVE = 0, XY_DEDUP_NEIGHBOUR = 1, XY_DEDUP_HASH = 2 };
 int xy_set_merge(xy_handle *h, int32_t dedup, int32_t edges_per_wave);
 
 /* Per-kernel timing with HIP events on the handle's stream: enable (1) or

@@ -148,8 +148,8 @@ class Lattices:
         return _lib.xy_get_sweep(self.h, rep)
 
     def set_merge(self, dedup: int, edges_per_wave: int = 1):
-        """Merge schedule: pair deduplication (_lib.XY_DEDUP_WAVE or XY_DEDUP_NEIGHBOUR)
-        and tile edges per wave (1 or 2)."""
+        """Merge schedule: pair deduplication (_lib.XY_DEDUP_WAVE, XY_DEDUP_NEIGHBOUR or
+        XY_DEDUP_HASH) and tile edges per wave (1, 2 or 4)."""
         _lib.xy_set_merge(self.h, dedup, edges_per_wave)
 
     def timing(self, enable: bool):

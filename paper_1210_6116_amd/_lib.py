@@ -22,7 +22,7 @@ XY_START_HOT, XY_START_COLD = 0, 1
 KERNEL_NAMES = ("bonds_ccl", "merge", "flip", "fused", "finalize", "coins", "sweep", "wrap", "flip_links2",
                 "labels_chosen")
 XY_PCC_HELICITY, XY_PCC_PERCOLATION = 0, 1
-XY_DEDUP_WAVE, XY_DEDUP_NEIGHBOUR = 0, 1
+XY_DEDUP_WAVE, XY_DEDUP_NEIGHBOUR, XY_DEDUP_HASH = 0, 1, 2
 
 
 class XYError(RuntimeError):

@@ -81,7 +81,8 @@ def merge_candidates():
     """The merge schedules timed: (pair deduplication, tile edges per wave)."""
     from . import _lib
 
-    return [(dd, epw) for dd in (_lib.XY_DEDUP_WAVE, _lib.XY_DEDUP_NEIGHBOUR) for epw in (1, 2, 4)]
+    return [(dd, epw) for dd in (_lib.XY_DEDUP_WAVE, _lib.XY_DEDUP_NEIGHBOUR, _lib.XY_DEDUP_HASH)
+            for epw in (1, 2, 4)]
 
 
 def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: int = 3, use_cache: bool = True):

@@ -910,7 +910,7 @@ int xy_set_merge(xy_handle *h, int32_t dedup, int32_t edges_per_wave)
 {
     int rc = check_handle(h);
     if (rc) return rc;
-    if (dedup != XY_DEDUP_WAVE && dedup != XY_DEDUP_NEIGHBOUR)
+    if (dedup != XY_DEDUP_WAVE && dedup != XY_DEDUP_NEIGHBOUR && dedup != XY_DEDUP_HASH)
         return fail(XY_EINVAL, "merge deduplication policy %d unknown", dedup);
     if (edges_per_wave != 1 && edges_per_wave != 2 && edges_per_wave != 4)
         return fail(XY_EINVAL, "edges_per_wave=%d is not 1, 2 or 4", edges_per_wave);

@@ -1234,12 +1234,32 @@ __device__ __forceinline__ EdgeLinks edge_links(const RepDesc *__restrict__ reps
 // every lane with the same pair drops out); dedup 1: a lane drops out only
 // when the lane before it holds the same pair (a tuning choice: the
 // partition, and so every root and coin, is the same either way).
+// dedup 2: one lane per pair found through a 64-entry table in the wave's
+// LDS (tab): every lane whose link asks for a union writes its index to the
+// entry its pair hashes to (the lowest lane wins) and leads if it won or if
+// the winner holds another pair (a collision: then copies of that pair may
+// all lead, and a union repeated changes nothing).
 template <int DEDUP>
-__device__ __forceinline__ bool leads(const EdgeLinks &e)
+__device__ __forceinline__ bool leads(const EdgeLinks &e, uint32_t *tab)
 {
     const int lane = threadIdx.x & 63;
     bool lead = false;
-    if constexpr (DEDUP == 0) {
+    if constexpr (DEDUP == 2) {
+        const bool want = e.on && e.a != e.b;
+        tab[lane] = 64u;
+        const uint32_t h = ((e.a ^ (e.b << 7)) * 0x9E3779B1u) >> 26;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (want) __hip_atomic_fetch_min(&tab[h], (uint32_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t w = want ? tab[h] & 63u : (uint32_t)lane;
+        const uint32_t wa = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(w << 2), (int)e.a);
+        const uint32_t wb = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(w << 2), (int)e.b);
+        lead = want && (w == (uint32_t)lane || wa != e.a || wb != e.b);
+    } else if constexpr (DEDUP == 0) {
         uint64_t todo = __ballot(e.on && e.a != e.b);
         while (todo) {
             const int l = __ffsll((long long)todo) - 1;
@@ -1276,7 +1296,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
         const int64_t gw = xcd_item(blockIdx.x - xcd_pad(nfin), kWaves, wave, nw);
         if (gw >= nw) return;
         const EdgeLinks e = edge_links<CUT>(reps, tile_rep, nrep, gtile0, gw, next_dir, cut);
-        if (leads<DEDUP>(e)) union_nodes(e.P, e.a, e.b);
+        __shared__ uint32_t tab_s[DEDUP == 2 ? kWaves * 64 : 1];
+        if (leads<DEDUP>(e, tab_s + (DEDUP == 2 ? wave * 64 : 0))) union_nodes(e.P, e.a, e.b);
     } else {
         // EPW tile edges per wave: their links read together, then the
         // leading pairs of all of them packed into the wave's lanes (through
@@ -1284,6 +1305,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
         // than one edge after the other
         __shared__ uint2 pair_s[kWaves][EPW * 64];
         __shared__ uint8_t edge_s[kWaves][EPW * 64];
+        __shared__ uint32_t tab_s[DEDUP == 2 ? kWaves * 64 : 1];
         EdgeLinks e[EPW];
         int ne = 0;  // edges of this wave (the same in every lane)
 #pragma unroll
@@ -1297,7 +1319,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
 #pragma unroll
         for (int q = 0; q < EPW; ++q) {
             if (q >= ne) break;
-            const bool lead = leads<DEDUP>(e[q]);
+            const bool lead = leads<DEDUP>(e[q], tab_s + (DEDUP == 2 ? wave * 64 : 0));
             const uint64_t bm = __ballot(lead);
             if (lead) {
                 const uint32_t r =
@@ -1897,14 +1919,16 @@ hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s
         hipLaunchKernelGGL(kern, grid, block, 0, s, lc.reps, lc.tile_rep, lc.fin_rep, lc.nrep, lc.gtile0,
                            lc.gtile_end, (int32_t)next_dir, nfin, (int32_t)0);
     };
-    if (lc.dedup == 0) {
-        if (epw == 1) go(k_merge<0, 1, false>);
-        else if (epw == 2) go(k_merge<0, 2, false>);
-        else go(k_merge<0, 4, false>);
-    } else {
-        if (epw == 1) go(k_merge<1, 1, false>);
-        else if (epw == 2) go(k_merge<1, 2, false>);
-        else go(k_merge<1, 4, false>);
+    switch (lc.dedup * 4 + epw) {
+    case 1: go(k_merge<0, 1, false>); break;
+    case 2: go(k_merge<0, 2, false>); break;
+    case 4: go(k_merge<0, 4, false>); break;
+    case 5: go(k_merge<1, 1, false>); break;
+    case 6: go(k_merge<1, 2, false>); break;
+    case 8: go(k_merge<1, 4, false>); break;
+    case 9: go(k_merge<2, 1, false>); break;
+    case 10: go(k_merge<2, 2, false>); break;
+    default: go(k_merge<2, 4, false>); break;
     }
     return hipGetLastError();
 }
@@ -1918,7 +1942,8 @@ hipError_t launch_merge_cut(const Launch &lc, int cut, hipStream_t s)
                            lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)0, (int64_t)0, (int32_t)cut);
     };
     if (lc.dedup == 0) go(k_merge<0, 1, true>);
-    else go(k_merge<1, 1, true>);
+    else if (lc.dedup == 1) go(k_merge<1, 1, true>);
+    else go(k_merge<2, 1, true>);
     return hipGetLastError();
 }
 
