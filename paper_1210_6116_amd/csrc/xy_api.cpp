@@ -382,11 +382,27 @@ hipError_t timed(xy_handle *h, int kind, F launch)
     e0 = take_event(h, &ev.b);
     if (e0 != hipSuccess) return e0;
     ev.kind = kind;
-    hipError_t e = hipEventRecord(ev.a, h->stream);
+    hipError_t e = hipSuccess;
+    if (kind == XY_K_WRAP) {
+        // several kernels: events around them on the stream
+        e = hipEventRecord(ev.a, h->stream);
+        if (e != hipSuccess) return e;
+        e = launch();
+        if (e != hipSuccess) return e;
+        e = hipEventRecord(ev.b, h->stream);
+    } else {
+        // one kernel: the events take its own start and end
+        xy::next_launch_events() = xy::KernelEvents{ev.a, ev.b};
+        e = launch();
+        const bool unused = xy::next_launch_events().start != nullptr;
+        xy::next_launch_events() = xy::KernelEvents{};
+        if (e != hipSuccess) return e;
+        if (unused) {  // nothing was launched: an empty interval
+            e = hipEventRecord(ev.a, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev.b, h->stream);
+        }
+    }
     if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(ev.b, h->stream);
     h->ev_used.push_back(ev);
     return e;
 }

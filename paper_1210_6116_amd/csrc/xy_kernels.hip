@@ -29,6 +29,7 @@
 // Built with -ffp-contract=off: the FP64 expressions below are evaluated
 // operation by operation, exactly as written.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <algorithm>
@@ -1837,29 +1838,53 @@ size_t lds_bytes_tile(int TH)
 // fewer than 2^32 work-items, and N reaches 2^32.
 constexpr int64_t kMaxStrideBlocks = 1 << 20;
 
+
+KernelEvents &next_launch_events()
+{
+    static thread_local KernelEvents ev;
+    return ev;
+}
+
+// Launch of a kernel; with events set by next_launch_events() (a timed
+// launch), the kernel's own start and end are recorded into them (the
+// dispatch's timestamps, not the stream's progress around it) and the events
+// are used up.
+template <typename K, typename... A>
+static void launch_k(K kern, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, A... args)
+{
+    KernelEvents &ev = next_launch_events();
+    if (ev.start) {
+        const KernelEvents e = ev;
+        ev = KernelEvents{};
+        hipExtLaunchKernelGGL(kern, grid, block, lds, s, e.start, e.stop, 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+    }
+}
+
 hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s)
 {
     const int64_t blocks = std::min<int64_t>((N + kThreads - 1) / kThreads, kMaxStrideBlocks);
-    hipLaunchKernelGGL(k_init_spins, dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, start);
+    launch_k(k_init_spins, dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, start);
     return hipGetLastError();
 }
 
 hipError_t launch_init_fourier(const RepDesc *d_reps, int32_t r, int64_t L, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init_fourier, dim3((unsigned)((L + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d_reps,
+    launch_k(k_init_fourier, dim3((unsigned)((L + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d_reps,
                        r);
     return hipGetLastError();
 }
 
 hipError_t launch_edge_refresh(const RepDesc *d_reps, int32_t r, int64_t ntiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_edge_refresh, dim3((unsigned)ntiles), dim3(128), 0, s, d_reps, r);
+    launch_k(k_edge_refresh, dim3((unsigned)ntiles), dim3(128), 0, s, d_reps, r);
     return hipGetLastError();
 }
 
 hipError_t launch_init_dir(const RepDesc *d_reps, int32_t nrep, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init_dir, dim3((nrep + 63) / 64), dim3(64), 0, s, d_reps, nrep);
+    launch_k(k_init_dir, dim3((nrep + 63) / 64), dim3(64), 0, s, d_reps, nrep);
     return hipGetLastError();
 }
 
@@ -1869,10 +1894,10 @@ static void tile_dispatch_bt(const Launch &lc, const FlipArgs &fa, hipStream_t s
     const size_t lds = lds_bytes_tile(lc.max_th);
     const dim3 grid((unsigned)xcd_blocks(lc.gtile_end - lc.gtile0, 1)), block(NW * 64);
     if (lc.big_index)
-        hipLaunchKernelGGL((k_tile<uint64_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
+        launch_k((k_tile<uint64_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
                            lc.gtile0, lc.gtile_end, fa);
     else
-        hipLaunchKernelGGL((k_tile<uint32_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
+        launch_k((k_tile<uint32_t, MODE, BT, NW>), grid, block, lds, s, lc.reps, lc.tile_rep, lc.nrep,
                            lc.gtile0, lc.gtile_end, fa);
 }
 
@@ -1916,7 +1941,7 @@ hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s
     const int64_t nfin = fin ? lc.nfin : 0;
     const dim3 grid((unsigned)(xcd_pad(nfin) + nblk)), block(kThreads);
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, grid, block, 0, s, lc.reps, lc.tile_rep, lc.fin_rep, lc.nrep, lc.gtile0,
+        launch_k(kern, grid, block, 0, s, lc.reps, lc.tile_rep, lc.fin_rep, lc.nrep, lc.gtile0,
                            lc.gtile_end, (int32_t)next_dir, nfin, (int32_t)0);
     };
     switch (lc.dedup * 4 + epw) {
@@ -1938,7 +1963,7 @@ hipError_t launch_merge_cut(const Launch &lc, int cut, hipStream_t s)
     if (cut != 1 && cut != 2) return hipErrorInvalidValue;
     const int64_t nblk = xcd_blocks(2 * (lc.gtile_end - lc.gtile0), kWaves);
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kThreads), 0, s, lc.reps, lc.tile_rep, lc.fin_rep,
+        launch_k(kern, dim3((unsigned)nblk), dim3(kThreads), 0, s, lc.reps, lc.tile_rep, lc.fin_rep,
                            lc.nrep, lc.gtile0, lc.gtile_end, (int32_t)0, (int64_t)0, (int32_t)cut);
     };
     if (lc.dedup == 0) go(k_merge<0, 1, true>);
@@ -1949,14 +1974,14 @@ hipError_t launch_merge_cut(const Launch &lc, int cut, hipStream_t s)
 
 hipError_t launch_copy_nodes(const Launch &lc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy_nodes, dim3((unsigned)(lc.gtile_end - lc.gtile0)), dim3(kThreads), 0, s, lc.reps,
+    launch_k(k_copy_nodes, dim3((unsigned)(lc.gtile_end - lc.gtile0)), dim3(kThreads), 0, s, lc.reps,
                        lc.tile_rep, lc.nrep, lc.gtile0);
     return hipGetLastError();
 }
 
 hipError_t launch_wrap(const Launch &lc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_wrap, dim3((unsigned)(2 * lc.nrep)), dim3(kThreads), 0, s, lc.reps);
+    launch_k(k_wrap, dim3((unsigned)(2 * lc.nrep)), dim3(kThreads), 0, s, lc.reps);
     return hipGetLastError();
 }
 
@@ -1967,7 +1992,7 @@ hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s)
     if (fin) fa = *fin;
     else std::memset(&fa, 0, sizeof fa);
     const int64_t nfin = fin ? lc.nrep : 0;
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)(xcd_pad(nfin) + xcd_blocks(ntile, kWaves))), dim3(kThreads), 0,
+    launch_k(k_resolve, dim3((unsigned)(xcd_pad(nfin) + xcd_blocks(ntile, kWaves))), dim3(kThreads), 0,
                        s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, nfin, fa);
     return hipGetLastError();
 }
@@ -1976,15 +2001,15 @@ hipError_t launch_measure(const Launch &lc, hipStream_t s)
 {
     const dim3 grid((unsigned)(lc.gtile_end - lc.gtile0)), block(kThreads);
     if (lc.big_index)
-        hipLaunchKernelGGL((k_measure<uint64_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+        launch_k((k_measure<uint64_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
     else
-        hipLaunchKernelGGL((k_measure<uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
+        launch_k((k_measure<uint32_t>), grid, block, 0, s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Launch &lc, const FlipArgs &fa, xy_obs *measure_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)lc.nfin), dim3(kThreads), 0, s, lc.reps, lc.fin_rep, lc.nrep, fa,
+    launch_k(k_finalize, dim3((unsigned)lc.nfin), dim3(kThreads), 0, s, lc.reps, lc.fin_rep, lc.nrep, fa,
                        measure_out);
     return hipGetLastError();
 }
@@ -1994,10 +2019,10 @@ hipError_t launch_flatten(const RepDesc *d_reps, int32_t r, int64_t N, bool big_
 {
     const int64_t blocks = std::min<int64_t>((N + kThreads - 1) / kThreads, kMaxStrideBlocks);
     if (big_index)
-        hipLaunchKernelGGL((k_flatten<uint64_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, d_out,
+        launch_k((k_flatten<uint64_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, d_out,
                            out_bits);
     else
-        hipLaunchKernelGGL((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, d_out,
+        launch_k((k_flatten<uint32_t>), dim3((unsigned)blocks), dim3(kThreads), 0, s, d_reps, r, d_out,
                            out_bits);
     return hipGetLastError();
 }

@@ -55,6 +55,13 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s, const FlipArgs
 // fin: also the first stage of the deferred finalisation of the previous,
 // fused sweep (the second runs with the edge coins, given its arguments).
 hipError_t launch_merge(const Launch &lc, bool next_dir, bool fin, hipStream_t s);
+
+// Events the next kernel launch on this thread records its own start and end
+// into (set by a caller that times one launch; used up by that launch).
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+KernelEvents &next_launch_events();
 // Wrapping check of the sweep labelled last (percolation rule): copies of the
 // boundary forest before the merge (copy_nodes), merges of the copies without
 // the links across the x seam (cut 1) / the y seam (cut 2), then the check
