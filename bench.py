@@ -284,8 +284,8 @@ def bench_batched(sweeps: int, nrep: int = 512):
                         "each; batched = one handle replayed from a %d-sweep HIP graph; plain = one handle per "
                         "replica, swept one after another; both with the autotuned tile height" % (nrep, sweeps, chunk),
             "tile_rows": rows, "autotune_ms_per_sweep": {str(k): v * 1e3 for k, v in sorted(tune_s.items())},
-            "merge_schedule": {"dedup": merge[0], "edges_per_wave": merge[1],
-                               "ms_per_sweep": {"%d,%d" % k: v * 1e3 for k, v in sorted(merge_s.items())}},
+            "merge_schedule": {"dedup": merge[0], "edges_per_wave": merge[1], "in_pass": merge[2],
+                               "ms_per_sweep": {"%d,%d,%d" % k: v * 1e3 for k, v in sorted(merge_s.items())}},
             "round_sweeps": chunk, "round_ms_p50": percentile(rounds, 50), "round_ms_p99": percentile(rounds, 99),
             "spins": total, "batched_value": sweeps * total / dt_b, "plain_value": sweeps * total / dt_p,
             "unit": "spin updates/s", "speedup": dt_p / dt_b}
@@ -347,8 +347,8 @@ def main():
     ap.add_argument("--beta", type=float, default=1.12)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--merge-schedule", default="",
-                    help="'dedup,edges_per_wave' for the L = 4096 lattice instead of the autotuner's pick (counter "
-                         "runs, whose slowed kernels can rank the choices differently)")
+                    help="'dedup,edges_per_wave[,in_pass]' for the L = 4096 lattice instead of the autotuner's pick "
+                         "(counter runs, whose slowed kernels can rank the choices differently)")
     ap.add_argument("--cpu-sweeps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
     ap.add_argument("--no-instrument", action="store_true", help="skip the instrumented pass")
@@ -398,7 +398,7 @@ def main():
     rows = args.tile_rows or 32
     # merge schedule picked by the autotuner for this lattice (timed here, not cached)
     if args.merge_schedule:
-        merge, merge_s = tuple(int(x) for x in args.merge_schedule.split(",")), {}
+        merge, merge_s = tuple(int(x) for x in (args.merge_schedule + ",0").split(",")[:3]), {}
     else:
         merge, merge_s = autotune.tune_merge([dict(L=L, beta=beta, seed=seed)], rows, use_cache=False)
     stream = torch.cuda.Stream()
@@ -495,8 +495,9 @@ def main():
                                "warm-up sweeps untimed, %d timed sweeps" % (L, beta, label_bits, THERM_SWEEPS,
                                                                             args.warmup, args.steps),
                    "L": L, "beta": beta, "seed": seed, "thermalisation": THERM_SWEEPS,
-                   "merge_schedule": {"dedup": merge[0], "edges_per_wave": merge[1],
-                                      "tuned_ms_per_sweep": {"%d,%d" % k: v * 1e3 for k, v in sorted(merge_s.items())}},
+                   "merge_schedule": {"dedup": merge[0], "edges_per_wave": merge[1], "in_pass": merge[2],
+                                      "tuned_ms_per_sweep": {"%d,%d,%d" % k: v * 1e3
+                                                             for k, v in sorted(merge_s.items())}},
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "valu_issue": valu_issue,

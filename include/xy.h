@@ -247,6 +247,20 @@ int xy_label_links_noalloc(int64_t L, int32_t label_bits, int32_t tile_rows, con
 enum { XY_DEDUP_WAVE = 0, XY_DEDUP_NEIGHBOUR = 1, XY_DEDUP_HASH = 2 };
 int xy_set_merge(xy_handle *h, int32_t dedup, int32_t edges_per_wave);
 
+/* The merge across tile edges inside the labelling tile pass (on = 1) instead
+ * of a merge kernel of its own (on = 0, the default): a tile that has stored
+ * its edge slots, boundary nodes and edge link masks (agent-scope stores,
+ * completed) counts itself at the four tile edges it touches, and the second
+ * of an edge's two tiles to arrive unites that edge's links (hash
+ * deduplication) before its block ends; no block waits for another.  The edge
+ * coins then also run both stages of a deferred finalisation and draw the next
+ * sweep's direction.  One kernel fewer per sweep, against unions in the tile
+ * pass's tail (a tuning choice, as xy_set_merge: the partition, and every
+ * label and coin, is the same either way).  Calls with the percolation rule
+ * keep the merge kernel (the wrapping check copies the forest before it).
+ * XY_EINVAL for on not 0 or 1. */
+int xy_set_merge_in_pass(xy_handle *h, int32_t on);
+
 /* Per-kernel timing with HIP events on the handle's stream: enable (1) or
  * disable (0) recording; read the accumulated milliseconds and launch counts
  * of each kernel class (XY_K_*) and reset them (synchronizes).  XY_K_SWEEP

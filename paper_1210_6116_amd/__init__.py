@@ -152,6 +152,10 @@ class Lattices:
         XY_DEDUP_HASH) and tile edges per wave (1, 2 or 4)."""
         _lib.xy_set_merge(self.h, dedup, edges_per_wave)
 
+    def set_merge_in_pass(self, on: bool):
+        """Unite the tile edges inside the labelling tile pass (no merge kernel)."""
+        _lib.xy_set_merge_in_pass(self.h, 1 if on else 0)
+
     def timing(self, enable: bool):
         _lib.xy_timing(self.h, enable)
 

@@ -90,6 +90,7 @@ _SIGS = {
     "xy_label_links_noalloc": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "xy_set_merge": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "xy_set_merge_in_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "xy_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "xy_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_int64, _P(ctypes.c_int64)]),
@@ -223,6 +224,10 @@ def xy_label_links_noalloc(L: int, label_bits: int, tile_rows: int, d_bx: int, d
 
 def xy_set_merge(h, dedup: int, edges_per_wave: int):
     _check(load().xy_set_merge(h, int(dedup), int(edges_per_wave)))
+
+
+def xy_set_merge_in_pass(h, on: int):
+    _check(load().xy_set_merge_in_pass(h, int(on)))
 
 
 def xy_timing(h, enable: bool):

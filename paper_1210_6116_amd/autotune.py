@@ -78,16 +78,18 @@ def tune(specs, sweeps: int = 20, warmup: int = 5, use_cache: bool = True):
 
 
 def merge_candidates():
-    """The merge schedules timed: (pair deduplication, tile edges per wave)."""
+    """The merge schedules timed: (pair deduplication, tile edges per wave, 0)
+    for the merge kernel, and (hash deduplication, 1, 1) for the merge inside
+    the labelling tile pass."""
     from . import _lib
 
-    return [(dd, epw) for dd in (_lib.XY_DEDUP_WAVE, _lib.XY_DEDUP_NEIGHBOUR, _lib.XY_DEDUP_HASH)
-            for epw in (1, 2, 4)]
+    return [(dd, epw, 0) for dd in (_lib.XY_DEDUP_WAVE, _lib.XY_DEDUP_NEIGHBOUR, _lib.XY_DEDUP_HASH)
+            for epw in (1, 2, 4)] + [(_lib.XY_DEDUP_HASH, 1, 1)]
 
 
 def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: int = 3, use_cache: bool = True):
-    """((dedup, edges per wave) fastest for these replicas at this tile height,
-    {(dedup, edges per wave): seconds per sweep}); cached like the tile height.
+    """((dedup, edges per wave, in pass) fastest for these replicas at this tile
+    height, {choice: seconds per sweep}); cached like the tile height.
 
     The choices are timed on one handle, thermalised by `warmup` sweeps first
     (the forest's shape, and with it the merge and the edge coins, depends on
@@ -95,7 +97,7 @@ def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: i
     schedule between blocks of `sweeps` sweeps, `repeats` rounds over all
     choices; a choice's time is its fastest block."""
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    key = _key(specs, arch) + "/rows%d/merge" % rows
+    key = _key(specs, arch) + "/rows%d/merge2" % rows
     path = _cache_path()
     cache = {}
     if os.path.exists(path):
@@ -106,7 +108,7 @@ def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: i
     if use_cache and key in cache:
         rec = cache[key]
         timings = {tuple(int(x) for x in k.split(",")): v * 1e-3 for k, v in rec["ms_per_sweep"].items()}
-        return (int(rec["dedup"]), int(rec["edges_per_wave"])), timings
+        return (int(rec["dedup"]), int(rec["edges_per_wave"]), int(rec["in_pass"])), timings
     from . import Lattices
 
     lat = Lattices([dict(s, tile_rows=rows) for s in specs])
@@ -123,8 +125,8 @@ def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: i
             timings[choice] = min(dt, timings.get(choice, dt))
     lat.close()
     best = min(timings, key=timings.get)
-    cache[key] = dict(dedup=best[0], edges_per_wave=best[1],
-                      ms_per_sweep={"%d,%d" % k: v * 1e3 for k, v in timings.items()})
+    cache[key] = dict(dedup=best[0], edges_per_wave=best[1], in_pass=best[2],
+                      ms_per_sweep={"%d,%d,%d" % k: v * 1e3 for k, v in timings.items()})
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         json.dump(cache, open(path, "w"), indent=1)
@@ -134,5 +136,6 @@ def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: i
 
 
 def configure(lat, choice):
-    """Applies a (dedup, edges per wave) choice of tune_merge to a handle."""
+    """Applies a (dedup, edges per wave, in pass) choice of tune_merge to a handle."""
     lat.set_merge(choice[0], choice[1])
+    lat.set_merge_in_pass(bool(choice[2]) if len(choice) > 2 else False)

@@ -143,6 +143,8 @@ int make_plan(const xy_params *p, int32_t n, Plan &P)
         off = align_up(off + (size_t)r.ntiles * 2 * sizeof(unsigned long long));
         l.ecoin = off;
         off = align_up(off + (size_t)r.ntiles * 4 * sizeof(unsigned long long));
+        l.ecnt = off;
+        off = align_up(off + (size_t)r.ntiles * 2 * sizeof(uint32_t));
         l.partials = off;
         off = align_up(off + (size_t)r.ntiles * xy::kNumSums * sizeof(double));
         l.partials2 = off;
@@ -185,6 +187,7 @@ void fill_desc(const Plan &P, int32_t k, const xy_params &p, char *A, xy::RepSta
     d.node = reinterpret_cast<unsigned long long *>(A + l.node);
     d.cross = reinterpret_cast<unsigned long long *>(A + l.cross);
     d.ecoin = reinterpret_cast<unsigned long long *>(A + l.ecoin);
+    d.ecnt = reinterpret_cast<uint32_t *>(A + l.ecnt);
     d.partials = reinterpret_cast<double *>(A + l.partials);
     d.partials2 = reinterpret_cast<double *>(A + l.partials2);
     d.fourier = reinterpret_cast<double *>(A + l.fourier);
@@ -310,6 +313,7 @@ struct xy_handle {
     char *perc_mem = nullptr;
     int32_t dedup = XY_DEDUP_WAVE;  // merge's pair deduplication and edges per wave (xy_set_merge)
     int32_t merge_epw = 1;
+    int32_t inpass = 0;             // the labelling tile pass unites the tile edges itself (xy_set_merge_in_pass)
     // captured sweep sequence (xy_sweep_graph)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -355,6 +359,7 @@ xy::Launch launch_all(xy_handle *h)
     lc.nfin = h->plan.total_fin;
     lc.dedup = h->dedup;
     lc.merge_epw = h->merge_epw;
+    lc.inpass = h->inpass;
     return lc;
 }
 
@@ -932,6 +937,15 @@ int xy_set_merge(xy_handle *h, int32_t dedup, int32_t edges_per_wave)
         return fail(XY_EINVAL, "edges_per_wave=%d is not 1, 2 or 4", edges_per_wave);
     h->dedup = dedup;
     h->merge_epw = edges_per_wave;
+    return XY_OK;
+}
+
+int xy_set_merge_in_pass(xy_handle *h, int32_t on)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (on != 0 && on != 1) return fail(XY_EINVAL, "xy_set_merge_in_pass: on=%d is not 0 or 1", on);
+    h->inpass = on;
     return XY_OK;
 }
 

@@ -188,6 +188,8 @@ struct RepDesc {
     unsigned long long *node;     // boundary-component forest
     unsigned long long *cross;    // links over the right / bottom tile edges
     unsigned long long *ecoin;    // per tile 4 words: flip coin of the cluster at every edge position
+    uint32_t *ecnt;          // per tile 2 counters (right, bottom edge): its tiles' arrivals in a tile pass
+                             // that unites the edges itself (zero between launches)
     float2 *edge[2];         // spins before sweep t in slot t&1: per tile, its first column (TH) then first row (TW)
     double *partials;        // kNumSums planes of per-tile sums: partials[k * ntiles + tile]
     double *partials2;       // chunk sums of the partials, fin_chunks x kNumSums
@@ -242,6 +244,8 @@ struct Tile {
     // tiles to the right and below (periodic; ntx and nty are powers of two)
     __device__ __forceinline__ int64_t right_tile() const { return (int64_t)ty * ntx + ((tx + 1) & (ntx - 1)); }
     __device__ __forceinline__ int64_t down_tile() const { return (int64_t)((ty + 1) & (nty - 1)) * ntx + tx; }
+    __device__ __forceinline__ int64_t left_tile() const { return (int64_t)ty * ntx + ((tx - 1) & (ntx - 1)); }
+    __device__ __forceinline__ int64_t up_tile() const { return (int64_t)((ty - 1) & (nty - 1)) * ntx + tx; }
 };
 
 template <typename IT>

@@ -31,7 +31,8 @@ struct Resolved {
 
 // Per-replica byte layout inside an arena.
 struct RepLayout {
-    size_t c, s, lab, bx[2], by[2], bxs, bys, bslot, node, cross, edge[2], ecoin, partials, partials2, fourier, end;
+    size_t c, s, lab, bx[2], by[2], bxs, bys, bslot, node, cross, edge[2], ecoin, ecnt, partials, partials2, fourier,
+        end;
 };
 
 struct Plan {
@@ -85,10 +86,15 @@ enum { NEXT_END = 0, NEXT_FUSE = 1, NEXT_SPEC = 2 };
 // edge coins (FUSE).  A sequence must end with NEXT_END.  timer(kind, launch)
 // runs each launch (and may bracket it with events).
 template <typename Timer>
-hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int32_t nrep, const xy::FlipArgs &fa,
+hipError_t enqueue_sweep_lc(const xy::Launch &lc_in, const xy::RepDesc *d_reps, int32_t nrep, const xy::FlipArgs &fa,
                             int next, Pipe &pp, hipStream_t s, Timer &&timer)
 {
     hipError_t e = hipSuccess;
+    // percolation rule: the wrapping check copies the forest before the
+    // merge, so the edges are united by the merge kernel, not in the tile pass
+    const bool perc = fa.rule == XY_PCC_PERCOLATION;
+    xy::Launch lc = lc_in;
+    if (perc) lc.inpass = 0;
     if (!pp.ready) {
         if (pp.spec)
             e = timer(XY_K_PLSEL, [&] { return xy::launch_tile(lc, xy::TILE_PLSEL, s); });
@@ -99,13 +105,17 @@ hipError_t enqueue_sweep_lc(const xy::Launch &lc, const xy::RepDesc *d_reps, int
     pp.spec = false;
     // percolation rule: the wrapping check of the sweep just labelled (forest
     // copies before the merge, their merges without the seam links after it)
-    const bool perc = fa.rule == XY_PCC_PERCOLATION;
     if (perc) {
         e = timer(XY_K_WRAP, [&] { return xy::launch_copy_nodes(lc, s); });
         if (e != hipSuccess) return e;
     }
-    e = timer(XY_K_MERGE, [&] { return xy::launch_merge(lc, true, pp.fin_pending, s); });
-    if (e != hipSuccess) return e;
+    // the merge kernel, unless the labelling tile pass united the edges
+    // (then the coins also draw the next direction and run both stages of a
+    // deferred finalisation)
+    if (!lc.inpass) {
+        e = timer(XY_K_MERGE, [&] { return xy::launch_merge(lc, true, pp.fin_pending, s); });
+        if (e != hipSuccess) return e;
+    }
     if (perc) {
         e = timer(XY_K_WRAP, [&] {
             hipError_t e2 = xy::launch_merge_cut(lc, 1, s);

@@ -295,6 +295,32 @@ __device__ void union_lds(uint32_t *lab, uint32_t a, uint32_t b)
     }
 }
 
+// --------------------------------------- hand-off between blocks of a launch
+// Data one block of a launch hands to another: stored with agent-scope
+// (relaxed atomic) accesses, which are coherent across the chip's L2 caches,
+// completed (stores_done) before the block signals with an atomic, and read
+// with agent-scope loads by a block that has seen the signal.  No L2
+// write-back or invalidation is needed: the plain stores and loads of a
+// launch stay in the L2 of their own XCD.
+template <typename T>
+__device__ __forceinline__ void st_agent(XY_G T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_agent(const XY_G T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until every store of the thread is complete (the agent-scope ones are
+// then visible to every block); the compiler moves no access across it.
+__device__ __forceinline__ void stores_done()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // ------------------------------------------- forest of boundary components
 // Entry of node n: (key << 32) | parent.  A root is its own parent; a parent's
 // key is never larger than its child's, so a root carries the smallest key,
@@ -488,6 +514,8 @@ __global__ __launch_bounds__(128) void k_edge_refresh(const RepDesc *__restrict_
         const uint64_t i = k < T.TH ? T.site(k, 0) : T.site(0, k - T.TH);
         e[k] = make_float2(R.c[i], R.s[i]);
     }
+    // the tile's edge arrival counts start at zero
+    if (threadIdx.x < 2) R.ecnt[2 * lt + threadIdx.x] = 0u;
 }
 
 // (cos, sin)(2 pi x / L) of every column x, for the Fourier sums.
@@ -519,6 +547,12 @@ __global__ void k_init_dir(const RepDesc *__restrict__ reps, int32_t nrep)
 // every loop over a wave's rows is unrolled and its independent loads are
 // issued together); BT = 0 is the general path (4 waves) for lattices
 // narrower than 64 and for batches of mixed tile shapes.
+// The unions of the links over tile edge (tile lt, edge 0 right / 1 bottom)
+// inside a labelling tile pass, by one wave, once both of its tiles have
+// handed over their slots, nodes and link masks; tab: the wave's 64 words of
+// LDS.
+__device__ void edge_unions_in_pass(const RepDesc &R, int64_t lt, int edge, uint32_t *tab);
+
 template <typename IT, int MODE, int BT, int NW>
 // Occupancy target: 7 waves per SIMD with 32-bit site indices (at most 72
 // VGPRs; 64 x 32 tiles take 18 KB of LDS per block), 6 with 64-bit indices.
@@ -1130,17 +1164,52 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
     if (p < NB) atomicMax(&lab_s[proot], kMark | (255u - (uint32_t)p));
     __syncthreads();
     // 4) edge slots and boundary nodes of the tile
+    //    (with fa.inpass other blocks of this launch read them: agent-scope
+    //    stores; plain ones otherwise, which the L2 combines)
+    auto put = [&](auto *p, auto v) {
+        if (fa.inpass) st_agent(p, v);
+        else *p = v;
+    };
     if (p < NB) {
         const uint32_t sl = slot_of(proot);
         const int64_t nbase = lt * NB;
-        gmem(R.bslot)[nbase + p] = (uint8_t)sl;
+        put(gmem(R.bslot) + nbase + p, (uint8_t)sl);
         if (sl == (uint32_t)p)
-            gmem(R.node)[nbase + p] =
-                ((unsigned long long)(uint32_t)T.site_of_local((int)proot) << 32) | (uint32_t)(nbase + p);
+            put(gmem(R.node) + nbase + p,
+                ((unsigned long long)(uint32_t)T.site_of_local((int)proot) << 32) | (uint32_t)(nbase + p));
     }
-    // 5) tile-local labels, and the links over the right and bottom edges.
-    //    The lane index is taken afresh (mbcnt) so that the site offsets of
-    //    the first loads need not stay live through the kernel.
+    //    and the links over the right and bottom edges
+    if (wave == 0) {
+        const bool xr = lane < TH && ((bxm[lane] >> (TW - 1)) & 1ull);
+        const uint64_t xm = __ballot(xr);
+        if (lane == 0) {
+            XY_G unsigned long long *cr = gmem(R.cross);
+            put(cr + 2 * lt, (unsigned long long)xm);
+            put(cr + 2 * lt + 1, (unsigned long long)(bym[TH - 1] & twmask));
+        }
+    }
+    // with fa.inpass the tile edges are united in this pass instead of by a
+    // merge kernel.  Once the tile's slots, nodes and masks above are
+    // complete, the tile counts itself at the four edges it touches (its
+    // right and bottom edges, the left tile's right edge, the upper tile's
+    // bottom edge); the second of an edge's two tiles to arrive unites that
+    // edge (one wave per edge, after the labels below) and clears its count
+    // for the next sweep.  No block waits for another.
+    uint32_t before = 0u;
+    int64_t owner = 0;
+    if (fa.inpass) {
+        stores_done();
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            const int q = threadIdx.x;
+            owner = q < 2 ? lt : q == 2 ? T.left_tile() : T.up_tile();
+            before = __hip_atomic_fetch_add(gmem(R.ecnt) + 2 * owner + (q & 1), 1u, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // 5) tile-local labels.  The lane index is taken afresh (mbcnt) so that
+    //    the site offsets of the first loads need not stay live through the
+    //    kernel.
     XY_G uint16_t *labn = gmem(R.lab);
     const int lane2 = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 #pragma unroll
@@ -1152,15 +1221,17 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
             else gel(labn, T.site(yb + k, lane2)) = v;
         }
     }
-    if (wave == 0) {
-        const bool xr = lane < TH && ((bxm[lane] >> (TW - 1)) & 1ull);
-        const uint64_t xm = __ballot(xr);
-        if (lane == 0) {
-            XY_G unsigned long long *cr = gmem(R.cross);
-            cr[2 * lt] = xm;
-            cr[2 * lt + 1] = bym[TH - 1] & twmask;
-        }
+    if (!fa.inpass) return;
+    // 6) the unions of the edges this tile reached second
+    __shared__ int64_t edge_owner[4];
+    __shared__ int edge_go[4];
+    if (threadIdx.x < 4) {
+        if (before == 1u) st_agent(gmem(R.ecnt) + 2 * owner + (threadIdx.x & 1), 0u);
+        edge_owner[threadIdx.x] = owner;
+        edge_go[threadIdx.x] = before == 1u;
     }
+    __syncthreads();
+    if (wave < 4 && edge_go[wave]) edge_unions_in_pass(R, edge_owner[wave], wave & 1, (uint32_t *)smem + wave * 64);
 }
 
 // ------------------------------------------------- merge across tiles
@@ -1177,9 +1248,11 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
 // fused flip both run beside work that runs anyway (stage 1 in the first
 // blocks of the merge, stage 2 in the first blocks of the edge coins); on its
 // own, k_finalize runs stage 1 and the last block of each replica stage 2.
+template <int U = 4>
 __device__ __forceinline__ void fin_chunk(const RepDesc *__restrict__ reps, const uint32_t *__restrict__ fin_rep,
-                                          int32_t nrep, int64_t b, double *red);
-__device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red);
+                                          int32_t nrep, int64_t b, double *red, bool agent = false);
+__device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red,
+                                            bool agent = false);
 
 // cut 0: the sweep's forest.  cut 1 / 2 (wrapping check): the copy node_cut[0]
 // / node_cut[1] of the forest, merged without the links that cross the
@@ -1276,6 +1349,31 @@ __device__ __forceinline__ bool leads(const EdgeLinks &e, uint32_t *tab)
     return lead;
 }
 
+__device__ void edge_unions_in_pass(const RepDesc &R, int64_t lt, int edge, uint32_t *tab)
+{
+    const int lane = threadIdx.x & 63;
+    const Tile<uint64_t> T = make_tile<uint64_t>(R, lt);
+    const int NB = R.nb;
+    EdgeLinks e;
+    e.nlinks = edge ? T.TW : T.TH;
+    e.a = 0;
+    e.b = 0;
+    // the two tiles' slots and the owner's mask, stored by blocks of this
+    // launch: agent-scope loads
+    const XY_G uint8_t *bsl = gmem(R.bslot);
+    const int64_t nt = edge ? T.down_tile() : T.right_tile();
+    if (lane < e.nlinks) {
+        const int pa = edge ? T.TW + lane : 2 * T.TW + T.TH + lane;  // own bottom row / right column
+        const int pn = edge ? lane : 2 * T.TW + lane;                 // neighbour's top row / left column
+        e.a = (uint32_t)(lt * NB) + ld_agent(bsl + lt * NB + pa);
+        e.b = (uint32_t)(nt * NB) + ld_agent(bsl + nt * NB + pn);
+    }
+    e.m = ld_agent(gmem(R.cross) + 2 * lt + edge);
+    e.on = lane < e.nlinks && ((e.m >> lane) & 1ull);
+    e.P = gmem(R.node);
+    if (leads<2>(e, tab)) union_nodes(e.P, e.a, e.b);
+}
+
 // DEDUP and EPW: the merge schedule (pair deduplication, tile edges per
 // wave); CUT: a forest copy of the wrapping check (cut 1 or 2)
 template <int DEDUP, int EPW, bool CUT>
@@ -1355,13 +1453,34 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
 // paths to the roots together, and the coins are exchanged by ballots.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_resolve(const RepDesc *__restrict__ reps,
                                                        const uint32_t *__restrict__ tile_rep, int32_t nrep,
-                                                       int64_t gtile0, int64_t gtile_end, int64_t nfin, FlipArgs fa)
+                                                       int64_t gtile0, int64_t gtile_end, int64_t nfin, FlipArgs fa,
+                                                       const uint32_t *__restrict__ fin_rep, int32_t inpass)
 {
-    // the first nfin blocks: deferred finalisation, stage 2 (the chunks of
-    // replica r, then the sweep; first in the grid, to overlap the coins)
+    // the first nfin blocks: deferred finalisation (first in the grid, to
+    // overlap the coins).  inpass == 0: stage 2 (the chunks of replica r,
+    // then the sweep); the merge kernel ran stage 1.  inpass != 0: no merge
+    // kernel ran: block b sums chunk b (stage 1), hands it over with an
+    // agent-scope store and counts itself in its replica's fin_done; the
+    // block that completes the count runs stage 2 and clears it.
     if (blockIdx.x < nfin) {
         __shared__ double red[kWaves * kNumSums];
-        fin_replica(reps[blockIdx.x], fa, nullptr, red);
+        if (!inpass) {
+            fin_replica(reps[blockIdx.x], fa, nullptr, red);
+            return;
+        }
+        __shared__ int last;
+        // (one tile per thread and round: the kernel is held to 64 VGPRs)
+        fin_chunk<1>(reps, fin_rep, nrep, blockIdx.x, red, true);
+        const RepDesc &R = reps[nrep == 1 ? 0 : fin_rep[blockIdx.x]];
+        if (threadIdx.x == 0) {
+            stores_done();
+            const uint32_t done = __hip_atomic_fetch_add(&R.st->fin_done, 1u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            last = done + 1 == (uint32_t)R.fin_chunks;
+            if (last) __hip_atomic_store(&R.st->fin_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (last) fin_replica(R, fa, nullptr, red, true);
         return;
     }
     constexpr int G = 4;  // groups of 64 edge positions
@@ -1372,6 +1491,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
     if (gtile >= gtile_end) return;
     int64_t lt;
     const RepDesc &R = rep_of(reps, tile_rep, nrep, gtile, lt);
+    // mirror direction of the sweep after the one labelled last (drawn by
+    // the merge kernel when there is one)
+    if (inpass && lt == 0 && lane == 0) compute_direction(R, R.st->tl + 1);
     const int NB = R.nb;
     const XY_G uint8_t *bs = gmem(R.bslot) + lt * NB;
     const XY_G unsigned long long *P = gmem(R.node);
@@ -1598,23 +1720,23 @@ __global__ __launch_bounds__(kThreads) void k_wrap(const RepDesc *__restrict__ r
 // Sums of the per-tile partials of replica R over the tiles [j0, j1), in a
 // fixed order (thread j takes tiles j0 + j, j0 + j + NT, ...); thread 0 gets
 // the totals.
-template <int NT>
+template <int NT, int U = 4>
 __device__ void sum_partials(const RepDesc &R, int64_t j0, int64_t j1, double (&tot)[kNumSums], double *red)
 {
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) tot[k] = 0.0;
     const int64_t nt = R.ntiles;
     const XY_G double *pt = gmem(R.partials);
-    // four tiles per thread per round, their loads issued together
+    // U tiles per thread per round, their loads issued together
     int64_t j = j0 + threadIdx.x;
-    for (; j + 3 * NT < j1; j += 4 * NT) {
-        double x[4][kNumSums];
+    for (; j + (U - 1) * NT < j1; j += U * NT) {
+        double x[U][kNumSums];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < U; ++q)
 #pragma unroll
             for (int k = 0; k < kNumSums; ++k) x[q][k] = pt[k * nt + j + q * NT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < U; ++q)
 #pragma unroll
             for (int k = 0; k < kNumSums; ++k) tot[k] += x[q][k];
     }
@@ -1710,21 +1832,26 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
 }
 
 // Stage 1: chunk b of the launch (replica fin_rep[b]) into its partials2 row.
+template <int U>
 __device__ __forceinline__ void fin_chunk(const RepDesc *__restrict__ reps, const uint32_t *__restrict__ fin_rep,
-                                          int32_t nrep, int64_t b, double *red)
+                                          int32_t nrep, int64_t b, double *red, bool agent)
 {
     const RepDesc &R = reps[nrep == 1 ? 0 : fin_rep[b]];
     const int64_t c = b - R.fin_base;
     double tot[kNumSums];
-    sum_partials<kThreads>(R, c * kFinSpan, std::min<int64_t>((c + 1) * kFinSpan, R.ntiles), tot, red);
+    sum_partials<kThreads, U>(R, c * kFinSpan, std::min<int64_t>((c + 1) * kFinSpan, R.ntiles), tot, red);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < kNumSums; ++k) gmem(R.partials2)[c * kNumSums + k] = tot[k];
+        for (int k = 0; k < kNumSums; ++k) {
+            if (agent) st_agent(gmem(R.partials2) + c * kNumSums + k, tot[k]);
+            else gmem(R.partials2)[c * kNumSums + k] = tot[k];
+        }
     }
 }
 
 // Stage 2: the chunk sums of replica R in a fixed order, then the sweep.
-__device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red)
+__device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red,
+                                            bool agent)
 {
     double tot[kNumSums];
 #pragma unroll
@@ -1732,7 +1859,7 @@ __device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa
     const XY_G double *p2 = gmem(R.partials2);
     for (int64_t c = threadIdx.x; c < R.fin_chunks; c += kThreads) {
 #pragma unroll
-        for (int k = 0; k < kNumSums; ++k) tot[k] += p2[c * kNumSums + k];
+        for (int k = 0; k < kNumSums; ++k) tot[k] += agent ? ld_agent(p2 + c * kNumSums + k) : p2[c * kNumSums + k];
     }
     block_sum<kNumSums, kWaves>(tot, red);
     if (threadIdx.x == 0) finish_sweep(R, fa, measure_out, tot);
@@ -1922,6 +2049,7 @@ hipError_t launch_tile(const Launch &lc, int mode, hipStream_t s, const FlipArgs
     FlipArgs f;
     if (fa) f = *fa;
     else std::memset(&f, 0, sizeof f);
+    f.inpass = lc.inpass;
     switch (mode) {
     case TILE_BONDS: tile_dispatch<M_BONDS>(lc, f, s); break;
     case TILE_FLIP: tile_dispatch<M_FLIP>(lc, f, s); break;
@@ -1991,9 +2119,11 @@ hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s)
     FlipArgs fa;
     if (fin) fa = *fin;
     else std::memset(&fa, 0, sizeof fa);
-    const int64_t nfin = fin ? lc.nrep : 0;
-    launch_k(k_resolve, dim3((unsigned)(xcd_pad(nfin) + xcd_blocks(ntile, kWaves))), dim3(kThreads), 0,
-                       s, lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, nfin, fa);
+    // the finalisation's blocks: one per replica (stage 2), or one per chunk
+    // (both stages) when the tile pass united the edges
+    const int64_t nfin = fin ? (lc.inpass ? lc.nfin : lc.nrep) : 0;
+    launch_k(k_resolve, dim3((unsigned)(xcd_pad(nfin) + xcd_blocks(ntile, kWaves))), dim3(kThreads), 0, s,
+             lc.reps, lc.tile_rep, lc.nrep, lc.gtile0, lc.gtile_end, nfin, fa, lc.fin_rep, (int32_t)lc.inpass);
     return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ struct Launch {
     const uint32_t *fin_rep;  // device: replica of every finalisation chunk (unused if nrep == 1)
     int64_t nfin;             // finalisation chunks of all replicas
     int32_t dedup = 0;        // merge: 0 one union per distinct node pair of a wave, 1 per run of equal neighbours
-    int32_t merge_epw = 1;    // merge: tile edges per wave (1 or 2)
+    int32_t merge_epw = 1;    // merge: tile edges per wave (1, 2 or 4)
+    int32_t inpass = 0;       // the labelling tile pass unites the tile edges (no merge kernel)
 };
 
 // Modes of the tile kernel.  TILE_SPEC: flip of sweep t and the links of
@@ -43,6 +44,8 @@ struct FlipArgs {
     double target;
     xy_obs *wmean;        // device: window means wmean[wrow * nrep + replica], or null
     int64_t wrow;
+    int32_t inpass;       // tile passes that label: unite the tile edges themselves (no merge kernel)
+    int32_t pad;
 };
 
 hipError_t launch_init_spins(const RepDesc *d_reps, int32_t r, int64_t N, int32_t start, hipStream_t s);
@@ -71,7 +74,9 @@ hipError_t launch_merge_cut(const Launch &lc, int cut, hipStream_t s);
 hipError_t launch_wrap(const Launch &lc, hipStream_t s);
 constexpr int64_t kWrapMaxL = 4096;  // largest side the wrapping check handles
 // Coins of the clusters at tile edges, after the merge; fin != null: the
-// second stage of a deferred finalisation.
+// second stage of a deferred finalisation.  With lc.inpass (the tile pass
+// united the edges, no merge kernel ran) it also runs the first stage and
+// draws the next sweep's direction.
 hipError_t launch_resolve(const Launch &lc, const FlipArgs *fin, hipStream_t s);
 hipError_t launch_measure(const Launch &lc, hipStream_t s);
 hipError_t launch_finalize(const Launch &lc, const FlipArgs &fa, xy_obs *measure_out, hipStream_t s);
