@@ -36,7 +36,8 @@ def test_more_than_one_gpu_is_refused():
 def test_counter_file_is_keyed_to_the_device_sources(tmp_path, monkeypatch):
     rec = json.load(open(bench.COUNTERS))
     assert len(rec["kernel_source_sha256"]) == 64
-    for k in ("fused", "merge", "coins"):
+    # (no merge kernel runs when the tile pass unites the tile edges)
+    for k in ("fused", "coins") + (("merge",) if "merge" in rec["kernels"] else ()):
         assert rec["kernels"][k]["fetch_kib"] > 0 and rec["kernels"][k]["valu_insts"] > 0
     # counters taken on other sources are not used
     stale = dict(rec, kernel_source_sha256="0" * 64)
