@@ -1188,25 +1188,6 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
             put(cr + 2 * lt + 1, (unsigned long long)(bym[TH - 1] & twmask));
         }
     }
-    // with fa.inpass the tile edges are united in this pass instead of by a
-    // merge kernel.  Once the tile's slots, nodes and masks above are
-    // complete, the tile counts itself at the four edges it touches (its
-    // right and bottom edges, the left tile's right edge, the upper tile's
-    // bottom edge); the second of an edge's two tiles to arrive unites that
-    // edge (one wave per edge, after the labels below) and clears its count
-    // for the next sweep.  No block waits for another.
-    uint32_t before = 0u;
-    int64_t owner = 0;
-    if (fa.inpass) {
-        stores_done();
-        __syncthreads();
-        if (threadIdx.x < 4) {
-            const int q = threadIdx.x;
-            owner = q < 2 ? lt : q == 2 ? T.left_tile() : T.up_tile();
-            before = __hip_atomic_fetch_add(gmem(R.ecnt) + 2 * owner + (q & 1), 1u, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
     // 5) tile-local labels.  The lane index is taken afresh (mbcnt) so that
     //    the site offsets of the first loads need not stay live through the
     //    kernel.
@@ -1222,13 +1203,26 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(
         }
     }
     if (!fa.inpass) return;
-    // 6) the unions of the edges this tile reached second
+    // 6) with fa.inpass the tile edges are united in this pass instead of by
+    //    a merge kernel.  Once the tile's slots, nodes and masks above are
+    //    complete (waited for after the labels, so that the stores of both
+    //    overlap), the tile counts itself at the four edges it touches (its
+    //    right and bottom edges, the left tile's right edge, the upper tile's
+    //    bottom edge); the second of an edge's two tiles to arrive unites that
+    //    edge (one wave per edge) and clears its count for the next sweep.
+    //    No block waits for another.
     __shared__ int64_t edge_owner[4];
     __shared__ int edge_go[4];
+    stores_done();
+    __syncthreads();
     if (threadIdx.x < 4) {
-        if (before == 1u) st_agent(gmem(R.ecnt) + 2 * owner + (threadIdx.x & 1), 0u);
-        edge_owner[threadIdx.x] = owner;
-        edge_go[threadIdx.x] = before == 1u;
+        const int q = threadIdx.x;
+        const int64_t owner = q < 2 ? lt : q == 2 ? T.left_tile() : T.up_tile();
+        XY_G uint32_t *cnt = gmem(R.ecnt) + 2 * owner + (q & 1);
+        const uint32_t before = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (before == 1u) st_agent(cnt, 0u);
+        edge_owner[q] = owner;
+        edge_go[q] = before == 1u;
     }
     __syncthreads();
     if (wave < 4 && edge_go[wave]) edge_unions_in_pass(R, edge_owner[wave], wave & 1, (uint32_t *)smem + wave * 64);
@@ -1248,7 +1242,7 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
 // fused flip both run beside work that runs anyway (stage 1 in the first
 // blocks of the merge, stage 2 in the first blocks of the edge coins); on its
 // own, k_finalize runs stage 1 and the last block of each replica stage 2.
-template <int U = 4>
+template <int U = 4, int KG = kNumSums>
 __device__ __forceinline__ void fin_chunk(const RepDesc *__restrict__ reps, const uint32_t *__restrict__ fin_rep,
                                           int32_t nrep, int64_t b, double *red, bool agent = false);
 __device__ __forceinline__ void fin_replica(const RepDesc &R, const FlipArgs &fa, xy_obs *measure_out, double *red,
@@ -1469,8 +1463,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
             return;
         }
         __shared__ int last;
-        // (one tile per thread and round: the kernel is held to 64 VGPRs)
-        fin_chunk<1>(reps, fin_rep, nrep, blockIdx.x, red, true);
+        // (four tiles per thread for four sums at a time: the kernel is held
+        // to 64 VGPRs)
+        fin_chunk<4, 4>(reps, fin_rep, nrep, blockIdx.x, red, true);
         const RepDesc &R = reps[nrep == 1 ? 0 : fin_rep[blockIdx.x]];
         if (threadIdx.x == 0) {
             stores_done();
@@ -1720,29 +1715,36 @@ __global__ __launch_bounds__(kThreads) void k_wrap(const RepDesc *__restrict__ r
 // Sums of the per-tile partials of replica R over the tiles [j0, j1), in a
 // fixed order (thread j takes tiles j0 + j, j0 + j + NT, ...); thread 0 gets
 // the totals.
-template <int NT, int U = 4>
+template <int NT, int U = 4, int KG = kNumSums>
 __device__ void sum_partials(const RepDesc &R, int64_t j0, int64_t j1, double (&tot)[kNumSums], double *red)
 {
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) tot[k] = 0.0;
     const int64_t nt = R.ntiles;
     const XY_G double *pt = gmem(R.partials);
-    // U tiles per thread per round, their loads issued together
-    int64_t j = j0 + threadIdx.x;
-    for (; j + (U - 1) * NT < j1; j += U * NT) {
-        double x[U][kNumSums];
+    // the sums in groups of KG; per group U tiles per thread per round, their
+    // loads issued together (every sum still adds its tiles in the same order)
 #pragma unroll
-        for (int q = 0; q < U; ++q)
+    for (int g = 0; g < kNumSums; g += KG) {
+        int64_t j = j0 + threadIdx.x;
+        for (; j + (U - 1) * NT < j1; j += U * NT) {
+            double x[U][KG];
 #pragma unroll
-            for (int k = 0; k < kNumSums; ++k) x[q][k] = pt[k * nt + j + q * NT];
+            for (int q = 0; q < U; ++q)
 #pragma unroll
-        for (int q = 0; q < U; ++q)
+                for (int k = 0; k < KG; ++k)
+                    if (g + k < kNumSums) x[q][k] = pt[(g + k) * nt + j + q * NT];
 #pragma unroll
-            for (int k = 0; k < kNumSums; ++k) tot[k] += x[q][k];
-    }
-    for (; j < j1; j += NT) {
+            for (int q = 0; q < U; ++q)
 #pragma unroll
-        for (int k = 0; k < kNumSums; ++k) tot[k] += pt[k * nt + j];
+                for (int k = 0; k < KG; ++k)
+                    if (g + k < kNumSums) tot[g + k] += x[q][k];
+        }
+        for (; j < j1; j += NT) {
+#pragma unroll
+            for (int k = 0; k < KG; ++k)
+                if (g + k < kNumSums) tot[g + k] += pt[(g + k) * nt + j];
+        }
     }
     block_sum<kNumSums, NT / 64>(tot, red);
 }
@@ -1832,14 +1834,14 @@ __device__ void finish_sweep(const RepDesc &R, const FlipArgs &fa, xy_obs *measu
 }
 
 // Stage 1: chunk b of the launch (replica fin_rep[b]) into its partials2 row.
-template <int U>
+template <int U, int KG>
 __device__ __forceinline__ void fin_chunk(const RepDesc *__restrict__ reps, const uint32_t *__restrict__ fin_rep,
                                           int32_t nrep, int64_t b, double *red, bool agent)
 {
     const RepDesc &R = reps[nrep == 1 ? 0 : fin_rep[b]];
     const int64_t c = b - R.fin_base;
     double tot[kNumSums];
-    sum_partials<kThreads, U>(R, c * kFinSpan, std::min<int64_t>((c + 1) * kFinSpan, R.ntiles), tot, red);
+    sum_partials<kThreads, U, KG>(R, c * kFinSpan, std::min<int64_t>((c + 1) * kFinSpan, R.ntiles), tot, red);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < kNumSums; ++k) {
