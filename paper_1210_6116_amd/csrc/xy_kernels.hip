@@ -555,8 +555,10 @@ __device__ void edge_unions_in_pass(const RepDesc &R, int64_t lt, int edge, uint
 
 template <typename IT, int MODE, int BT, int NW>
 // Occupancy target: 7 waves per SIMD with 32-bit site indices (at most 72
-// VGPRs; 64 x 32 tiles take 18 KB of LDS per block), 6 with 64-bit indices.
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(sizeof(IT) == 4 ? 7 : 6))) void k_tile(
+// VGPRs; 64 x 32 tiles take 18 KB of LDS per block), 6 with 64-bit indices,
+// except for M_SPEC (7: its few spills cost less than the wave gained).
+__global__ __launch_bounds__(NW * 64)
+__attribute__((amdgpu_waves_per_eu(sizeof(IT) == 4 ? 7 : (MODE == M_SPEC ? 7 : 6)))) void k_tile(
     const RepDesc *__restrict__ reps, const uint32_t *__restrict__ tile_rep, int32_t nrep, int64_t gtile0,
     int64_t gtile_end, FlipArgs fa)
 {
