@@ -195,10 +195,25 @@ def bench_l65536(sweeps: int):
     import paper_1210_6116_amd as xy
     import xyworkloads as wl
 
+    from paper_1210_6116_amd import autotune
+
     L = 65536
+    spec = dict(L=L, beta=1.0, seed=wl.SEED_L65536, label_bits=64)
+
+    def pcc_step(h, n):
+        h.pcc(n, 1, 0.004, dbeta_min=0.0005, halve_every=250)
+
+    # merge schedule for this workload, timed by the autotuner on its own PCC
+    # call (a short budget: blocks of a few sweeps of 2^32 sites separate the
+    # choices)
+    t0 = time.perf_counter()
+    merge, merge_ms = autotune.tune_merge([spec], 32, sweeps=6, warmup=20, repeats=2, step=pcc_step, tag="pcc-w1")
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
-    lat = xy.Lattices(dict(L=L, beta=1.0, seed=wl.SEED_L65536, label_bits=64), stream=stream)
+    lat = xy.Lattices(spec, stream=stream)
+    autotune.configure(lat, merge)
     torch.cuda.synchronize()
     t_alloc = time.perf_counter() - t0
     lat.pcc(2, 1, 0.004, dbeta_min=0.0005, halve_every=250)  # warm-up steps
@@ -224,7 +239,10 @@ def bench_l65536(sweeps: int):
             "sweep_ms_p50": percentile(per, 50), "sweep_ms_p99": percentile(per, 99),
             "kernels_ms": {k: ms[i] / n[i] for i, k in enumerate(xy._lib.KERNEL_NAMES) if n[i] and k != "sweep"},
             "beta_after": beta, "beta_trace_every": every, "beta_trace": beta_trace,
-            "arena_GB": arena_gb, "alloc_init_s": t_alloc}
+            "arena_GB": arena_gb, "alloc_init_s": t_alloc,
+            "merge_schedule": {"dedup": merge[0], "edges_per_wave": merge[1], "in_pass": merge[2],
+                               "tuned_ms_per_sweep": {"%d,%d,%d" % k: v * 1e3 for k, v in merge_ms.items()},
+                               "tune_s": t_tune}}
 
 
 def bench_batched(sweeps: int, nrep: int = 512):
@@ -512,7 +530,7 @@ def main():
         deadline = t_start + args.time_budget
         # rough wall time of each leg at MI355X speed (seconds), to skip a leg
         # that would run past the budget rather than be cut off by a caller
-        est = {"l65536": 8.0 + 0.04 * args.l65536_sweeps, "batched": 12.0 + 0.025 * args.batched_sweeps,
+        est = {"l65536": 16.0 + 0.04 * args.l65536_sweeps, "batched": 12.0 + 0.025 * args.batched_sweeps,
                # the served pass: requests x mean L^2 (1.49e7 for L = 256..8192) x mean sweeps at ~1e11 updates/s
                # (the sequential pass after it stops starting requests at the deadline)
                "serving": 10.0 + args.serve_requests * 1.49e7 * (args.serve_sweeps_lo + args.serve_sweeps_hi) / 2.0

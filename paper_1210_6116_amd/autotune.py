@@ -87,7 +87,8 @@ def merge_candidates():
             for epw in (1, 2, 4)] + [(_lib.XY_DEDUP_HASH, 1, 1)]
 
 
-def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: int = 3, use_cache: bool = True):
+def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: int = 3, use_cache: bool = True,
+               step=None, tag: str = ""):
     """((dedup, edges per wave, in pass) fastest for these replicas at this tile
     height, {choice: seconds per sweep}); cached like the tile height.
 
@@ -95,9 +96,15 @@ def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: i
     (the forest's shape, and with it the merge and the edge coins, depends on
     the state: a hot start ranks the choices differently), switching the
     schedule between blocks of `sweeps` sweeps, `repeats` rounds over all
-    choices; a choice's time is its fastest block."""
+    choices; a choice's time is its fastest block.  step(lat, n): how n sweeps
+    of the workload are run (default: plain sweeps; a PCC run passes its own
+    call, since its window ends run other tile passes); tag names it in the
+    cache key."""
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    key = _key(specs, arch) + "/rows%d/merge2" % rows
+    key = _key(specs, arch) + "/rows%d/merge2" % rows + ("/" + tag if tag else "")
+    if step is None:
+        def step(lat, n):
+            lat.sweep(n)
     path = _cache_path()
     cache = {}
     if os.path.exists(path):
@@ -112,14 +119,14 @@ def tune_merge(specs, rows: int, sweeps: int = 50, warmup: int = 200, repeats: i
     from . import Lattices
 
     lat = Lattices([dict(s, tile_rows=rows) for s in specs])
-    lat.sweep(warmup)
+    step(lat, warmup)
     timings = {}
     for _ in range(repeats):
         for choice in merge_candidates():
             configure(lat, choice)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            lat.sweep(sweeps)
+            step(lat, sweeps)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t) / sweeps
             timings[choice] = min(dt, timings.get(choice, dt))
