@@ -93,3 +93,35 @@ def test_results_do_not_depend_on_merge_schedule(beta):
         for k in range(len(specs)):
             assert np.array_equal(st[k][0], ref[2][k][0]) and np.array_equal(st[k][1], ref[2][k][1]), (choice, k)
             assert np.array_equal(lab[k], ref[3][k]), (choice, k)
+
+
+def test_merge_schedule_tuned_on_a_pcc_call(tmp_path, monkeypatch):
+    """tune_merge timing the workload's own call (window-1 PCC, whose window
+    ends run the two-candidate and chosen-labels passes): every choice timed,
+    the pick cached under its tag apart from the plain-sweep record, and every
+    choice gives the same beta trace and state."""
+    import paper_1210_6116_amd as xy
+    from paper_1210_6116_amd import autotune
+    monkeypatch.setenv("XDG_CACHE_HOME", str(tmp_path))
+    spec = dict(L=256, beta=1.0, seed=0xCAFE)
+
+    def pcc_step(lat, n):
+        lat.pcc(n, 1, 0.004, dbeta_min=0.0005, halve_every=50)
+
+    best, timings = autotune.tune_merge([spec], 32, sweeps=4, warmup=4, repeats=1, use_cache=False,
+                                        step=pcc_step, tag="pcc-w1")
+    print("pcc merge schedule:", best, flush=True)
+    assert set(timings) == set(autotune.merge_candidates()) and timings[best] == min(timings.values())
+    again, cached = autotune.tune_merge([spec], 32, step=pcc_step, tag="pcc-w1")
+    assert again == best and cached == pytest.approx(timings)
+    runs = {}
+    for choice in autotune.merge_candidates():
+        lat = xy.Lattices(spec)
+        autotune.configure(lat, choice)
+        means = lat.pcc(30, 1, 0.004, dbeta_min=0.0005, halve_every=50, means=True)
+        runs[choice] = (means[:, 0]["beta"].copy(), lat.get_state())
+        lat.close()
+    ref_beta, (ref_c, ref_s) = runs[autotune.merge_candidates()[0]]
+    for choice, (beta, (c, s)) in runs.items():
+        assert np.array_equal(beta, ref_beta), choice
+        assert np.array_equal(c, ref_c) and np.array_equal(s, ref_s), choice
