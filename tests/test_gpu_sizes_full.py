@@ -36,11 +36,16 @@ OBS_TOL = 1e-10
 NAMES = ("E", "m2", "ex", "sx", "ey", "sy", "ups_x", "mk2")
 
 
-def test_full_size_l4096_fused_sweeps():
+@pytest.mark.parametrize("merge", [(0, 1, 0), (2, 1, 1)])
+def test_full_size_l4096_fused_sweeps(merge):
+    # the default merge schedule, and the one the bench's tuner picks for this
+    # lattice (hash deduplication, the merge inside the labelling pass)
     import paper_1210_6116_amd as xy
+    from paper_1210_6116_amd import autotune
     L, beta, seed = 4096, 1.12, wl.SEED_L4096
-    print("L=4096 fused sweeps", flush=True)
+    print("L=4096 fused sweeps, merge schedule %s" % (merge,), flush=True)
     lat = xy.Lattices(dict(L=L, beta=beta, seed=seed))
+    autotune.configure(lat, merge)
     c0, s0 = wl.random_spins(L, 4097)
     lat.set_state(c0, s0)
     orc = oracle.Lattice(L=L, beta=beta, seed=seed, storage32=True, c=c0.astype(np.float64),
