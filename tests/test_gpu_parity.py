@@ -171,9 +171,11 @@ def test_batched_replicas_match_plain():
 
 def test_batched_512_replicas_sampled_against_oracle():
     # The batched workload at its full shape (512 replicas, L = 64 ... 2048, beta in
-    # [1.0, 1.2], 64-row tiles, sweeps replayed from a captured graph): two
-    # replicas of every size, L = 64 ... 2048, are checked against the oracle bit
-    # for bit (the L = 512 ... 2048 replicas carry most of the batch's work)
+    # [1.0, 1.2], 64-row tiles, the merge schedule the bench's tuner picks for it:
+    # hash deduplication, 4 tile edges per merge wave; sweeps replayed from a
+    # captured graph): two replicas of every size, L = 64 ... 2048, are checked
+    # against the oracle bit for bit (the L = 512 ... 2048 replicas carry most of
+    # the batch's work)
     xy = _gpu()
     specs = [dict(sp, tile_rows=64) for sp in wl.batched_replicas(512)]
     picks = []
@@ -182,6 +184,7 @@ def test_batched_512_replicas_sampled_against_oracle():
     assert len(picks) == 12
     print("512-replica batch, sampled replicas %s" % picks, flush=True)
     batch = xy.Lattices(specs)
+    batch.set_merge(2, 4)
     nsw = 3
     batch.sweep_graph(nsw, 1)
     meas = batch.measure()
